@@ -1,0 +1,424 @@
+"""Pins of the oracle against facts that do not come from the oracle itself:
+an independent Philox implementation, closed-form laws (inverse Gaussian,
+Wald's identities, AR(1) stationary variance, explicit-Euler amplification),
+an independent deterministic ODE solve, the exact overdamped mean first
+passage time by quadrature, the Kramers rate, numbers the paper prints, and a
+50-digit brute-force re-implementation on tiny inputs.
+
+CPU only (no GPU marker)."""
+
+import json
+import math
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def dU(g):
+    """Barrier height of the tilted washboard -cos(phi) - g*phi (V0 = 1)."""
+    return 2.0 * (math.sqrt(1.0 - g * g) - g * math.acos(g))
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10 against PyTorch's independent header-only implementation
+
+
+@pytest.fixture(scope="module")
+def torch_philox(tmp_path_factory):
+    import torch
+
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    exe = str(tmp_path_factory.mktemp("philox") / "xcheck")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-I" + inc,
+                           os.path.join(HERE, "philox_xcheck.cpp"), "-o", exe])
+
+    def run(triples):
+        inp = "".join(f"{s} {r} {b}\n" for s, r, b in triples)
+        out = subprocess.check_output([exe], input=inp, text=True)
+        return [[int(w, 16) for w in line.split()] for line in out.strip().split("\n")]
+
+    return run
+
+
+def test_philox_matches_independent_implementation(oracle_mod, torch_philox):
+    rng = np.random.Generator(np.random.PCG64(123))
+    triples = [(0, 0, 0), (1, 0, 0), (2**64 - 1, 2**64 - 1, 2**64 - 1), (1, 5, 7),
+               (0xDEADBEEFCAFEF00D, 2**32, 2**32 - 1)]
+    for _ in range(400):
+        s, r, b = (int(x) for x in rng.integers(0, 2**63, size=3, dtype=np.uint64))
+        # exercise the high halves as well
+        triples.append((s * 2 + 1, r, b >> int(rng.integers(0, 40))))
+    ref = torch_philox(triples)
+    for (s, r, b), words in zip(triples, ref):
+        got = [int(x) for x in oracle_mod.rng_words(s, r, b)]
+        assert got == words, (s, r, b)
+    # the raw (ctr, key) entry point is the same function
+    s, r, b = triples[7]
+    ctr = [b & 0xFFFFFFFF, b >> 32, r & 0xFFFFFFFF, r >> 32]
+    key = [s & 0xFFFFFFFF, s >> 32]
+    assert [int(x) for x in oracle_mod.philox4x32_10(ctr, key)] == ref[7]
+
+
+# ---------------------------------------------------------------------------
+# Box-Muller normals
+
+
+def test_box_muller_pair_invariants(oracle_mod):
+    # z0^2 + z1^2 = -2 ln u0 and atan2(z1, z0) = 2 pi u1 (mod 2 pi), where
+    # u = (x + 1/2) 2^-32 from the Philox words of the same block.
+    for blk in range(200):
+        w = oracle_mod.rng_words(99, 3, blk).astype(np.float64)
+        z = oracle_mod.normals(99, 3, blk)
+        u = (w + 0.5) / 2.0**32
+        for pair in range(2):
+            a, b = u[2 * pair], u[2 * pair + 1]
+            z0, z1 = z[2 * pair], z[2 * pair + 1]
+            assert z0 * z0 + z1 * z1 == pytest.approx(-2.0 * math.log(a), rel=1e-12)
+            ang = math.atan2(z1, z0) % (2 * math.pi)
+            d = abs(ang - 2 * math.pi * b)
+            assert min(d, 2 * math.pi - d) < 1e-9
+
+
+def test_normals_are_standard_gaussian(oracle_mod):
+    z = np.concatenate([oracle_mod.normals(7, r, b) for r in range(50) for b in range(1000)])
+    n = z.size
+    assert abs(z.mean()) < 4.0 / math.sqrt(n)
+    assert abs(z.var() - 1.0) < 4.0 * math.sqrt(2.0 / n)
+    assert abs(stats.skew(z)) < 4.0 * math.sqrt(6.0 / n)
+    assert abs(stats.kurtosis(z)) < 4.0 * math.sqrt(24.0 / n)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    # smallest uniform is 2^-33, so |z| <= sqrt(66 ln 2)
+    assert np.abs(z).max() <= math.sqrt(66.0 * math.log(2.0))
+    # consecutive draws (the per-step noise sequence) are uncorrelated
+    r = np.corrcoef(z[:-1], z[1:])[0, 1]
+    assert abs(r) < 4.0 / math.sqrt(n)
+
+
+# ---------------------------------------------------------------------------
+# Zero potential, overdamped: a Gaussian random walk with drift gamma*dt and
+# step variance 2*T*dt.  Wald's identities hold exactly for the discrete chain
+# at the first passage step K; the passage time law is inverse Gaussian.
+
+
+@pytest.fixture(scope="module")
+def drift_diffusion(oracle_mod):
+    g, T, a, dt = 1.0, 0.1, 2.0, 0.01
+    p = oracle_mod.OracleParams(model=1, V0=0.0, alpha=0.0, T=T, gamma0=g, dt=dt,
+                                phi0=0.0, v0=0.0, threshold=a, max_steps=10**8, seed=7)
+    steps, phi = oracle_mod.escape_steps(p, 0, 20000, with_phi=True)
+    return dict(g=g, T=T, a=a, dt=dt, steps=steps, phi=phi)
+
+
+def test_wald_identities(drift_diffusion):
+    d = drift_diffusion
+    sig2 = 2.0 * d["T"] * d["dt"]
+    k = d["steps"].astype(np.float64)
+    assert (k > 0).all()
+    D = d["phi"] - d["g"] * d["dt"] * k  # S_K - mu K
+    n = D.size
+    # first identity: E[S_K] = mu E[K]
+    assert abs(D.mean()) < 4.0 * D.std() / math.sqrt(n)
+    # second identity: E[(S_K - mu K)^2] = sigma^2 E[K]
+    assert (D**2).mean() / (sig2 * k.mean()) == pytest.approx(1.0, abs=0.04)
+
+
+def test_inverse_gaussian_first_passage(drift_diffusion):
+    d = drift_diffusion
+    sig = math.sqrt(2.0 * d["T"] * d["dt"])
+    # continuous-time FPT of level a is IG(a/g, a^2/(2T)); discrete monitoring
+    # is corrected by Siegmund's barrier shift 0.5826 sigma
+    a = d["a"] + 0.5826 * sig
+    mean, shape = a / d["g"], a * a / (2.0 * d["T"])
+    s = np.sort(d["steps"])
+    n = s.size
+    kk = np.arange(1, s.max() + 1)
+    emp = np.searchsorted(s, kk, side="right") / n
+    model = stats.invgauss.cdf(kk * d["dt"], mean / shape, scale=shape)
+    assert np.abs(emp - model).max() < 1.63 / math.sqrt(n) + 0.002
+    assert s.mean() * d["dt"] == pytest.approx(mean, abs=3 * s.std() * d["dt"] / math.sqrt(n))
+
+
+# ---------------------------------------------------------------------------
+# Zero potential, underdamped: v is the AR(1) chain v_k = (1 - h alpha) v_{k-1}
+# + sigma r_k with sigma^2 = 2 alpha T h, stationary variance T / (1 - h alpha/2)
+# and lag-one autocorrelation 1 - h alpha.
+
+
+def test_underdamped_free_velocity_is_ar1(oracle_mod):
+    alpha, T, h = 0.5, 0.3, 0.05
+    p = oracle_mod.OracleParams(model=0, V0=0.0, alpha=alpha, T=T, gamma0=0.0, dt=h,
+                                phi0=0.0, v0=0.0, threshold=1e300, max_steps=1, seed=3)
+    vs = []
+    for rep in range(20):
+        phi, v = oracle_mod.trajectory(p, rep, 100000)
+        vs.append(v[2000:])
+        # explicit Euler: the phase moves with the velocity of the previous step
+        assert np.allclose(np.diff(phi), h * v[:-1], rtol=0, atol=1e-12)
+    v = np.concatenate(vs)
+    assert v.var() == pytest.approx(T / (1.0 - h * alpha / 2.0), rel=0.03)
+    lag1 = np.mean([np.corrcoef(x[:-1], x[1:])[0, 1] for x in vs])
+    assert lag1 == pytest.approx(1.0 - h * alpha, abs=0.002)
+
+
+# ---------------------------------------------------------------------------
+# Noise-free, small oscillation around phi = 0 (gamma = 0): the explicit Euler
+# map [[1, h], [-h, 1 - h alpha]] has determinant 1 - h alpha + h^2, so the
+# energy phi^2 + v^2 decays by that factor per step (a semi-implicit scheme
+# would give 1 - h alpha; the exact flow e^{-alpha h}).
+
+
+def test_explicit_euler_amplification(oracle_mod):
+    alpha, h = 0.02, 0.01
+    p = oracle_mod.OracleParams(model=0, V0=1.0, alpha=alpha, T=0.0, gamma0=0.0, dt=h,
+                                phi0=1e-4, v0=0.0, threshold=1.0, max_steps=1, seed=1)
+    n = 200000
+    phi, v = oracle_mod.trajectory(p, 0, n)
+    E = phi**2 + v**2
+    period = int(round(2 * math.pi / h))
+    e0 = E[:period].mean()
+    e1 = E[-period:].mean()
+    rate = math.log(e1 / e0) / (n - period)
+    assert rate == pytest.approx(math.log(1.0 - h * alpha + h * h), rel=0.01)
+
+
+# ---------------------------------------------------------------------------
+# Noise-free ramp: no switching while gamma_k <= 1 (dt <= alpha), and the
+# switching time equals an independent high-order ODE solve of
+# phi'' + alpha phi' + sin(phi) = ramp*t up to the Euler O(dt) error.
+
+
+@pytest.mark.parametrize("ramp", [1e-3, 3e-4])
+def test_deterministic_switching(oracle_mod, ramp):
+    from scipy.integrate import solve_ivp
+
+    alpha = 0.1
+
+    def rhs(t, y):
+        return [y[1], -alpha * y[1] - math.sin(y[0]) + ramp * t]
+
+    def hit(t, y):
+        return y[0] - 2 * math.pi
+
+    hit.terminal, hit.direction = True, 1
+    sol = solve_ivp(rhs, [0, 1.2 / ramp], [0.0, 0.0], method="DOP853", rtol=1e-11,
+                    atol=1e-12, events=hit)
+    t_star = sol.t_events[0][0]
+    errs = []
+    for dt in (0.01, 0.005):
+        p = oracle_mod.OracleParams(model=0, alpha=alpha, T=0.0, gamma0=0.0, ramp=ramp,
+                                    dt=dt, phi0=0.0, v0=0.0, threshold=2 * math.pi,
+                                    max_steps=10**9, seed=1)
+        k = int(oracle_mod.escape_steps(p, 0, 1)[0])
+        assert k > 0
+        assert ramp * dt * k > 1.0  # never before gamma reaches 1
+        errs.append(abs(k * dt - t_star))
+    assert errs[0] < 10 * 0.01
+    assert errs[1] <= errs[0] + 0.005
+
+
+# ---------------------------------------------------------------------------
+# Overdamped escape over a full period: exact mean first passage time of the
+# continuous process by the double quadrature
+#   tau = (1/T) int_{x0}^{b} dy e^{U(y)/T} int_{-inf}^{y} e^{-U(z)/T} dz,
+# U = -cos(phi) - gamma phi.
+
+
+def mfpt_overdamped(g, T, x0, b):
+    def U(x):
+        return -math.cos(x) - g * x
+
+    lo = x0 - 60.0
+
+    def inner(y):
+        return integrate.quad(lambda z: math.exp(-(U(z) - U(y)) / T), lo, y, limit=400)[0]
+
+    return integrate.quad(inner, x0, b, limit=400)[0] / T
+
+
+def test_overdamped_mfpt_quadrature(oracle_mod):
+    g, T, dt = 0.8, 0.2, 0.005
+    x0 = math.asin(g)
+    tau = mfpt_overdamped(g, T, x0, x0 + 2 * math.pi)
+    p = oracle_mod.OracleParams(model=1, alpha=0.0, T=T, gamma0=g, dt=dt, phi0=x0,
+                                v0=0.0, threshold=x0 + 2 * math.pi, max_steps=10**9,
+                                seed=11)
+    s = oracle_mod.escape_steps(p, 0, 8000) * dt
+    se = s.std() / math.sqrt(s.size)
+    assert abs(s.mean() - tau) < 3.0 * se + 0.015 * tau
+
+
+def test_overdamped_quadrature_reproduces_config_value():
+    # the uneven-load workload (gamma 0.8, T 0.05): tau = 356.8 time units,
+    # above the Kramers-Smoluchowski estimate 2 pi / sqrt(1-g^2) e^{dU/T}
+    g, T = 0.8, 0.05
+    x0 = math.asin(g)
+    tau = mfpt_overdamped(g, T, x0, x0 + 2 * math.pi)
+    ks = 2 * math.pi / math.sqrt(1 - g * g) * math.exp(dU(g) / T)
+    assert tau == pytest.approx(356.8, abs=0.1)
+    assert 1.0 < tau / ks < 1.25
+
+
+# ---------------------------------------------------------------------------
+# Underdamped Kramers rate (moderate damping): r = (omega_a / 2 pi)
+# (sqrt(alpha^2/4 + omega_b^2) - alpha/2) / omega_b e^{-dU/T}; and the Arrhenius
+# slope d ln<tau> / d(1/T) recovers the barrier height dU.
+
+
+def test_underdamped_kramers_rate_and_arrhenius_slope(oracle_mod):
+    g, alpha, dt = 0.8, 0.5, 0.02
+    wa = wb = (1 - g * g) ** 0.25
+    lam = math.sqrt(alpha**2 / 4 + wb**2) - alpha / 2
+    x0 = math.asin(g)
+    means = {}
+    for ratio in (4.0, 5.0):
+        T = dU(g) / ratio
+        p = oracle_mod.OracleParams(model=0, alpha=alpha, T=T, gamma0=g, dt=dt, phi0=x0,
+                                    v0=0.0, threshold=x0 + 2 * math.pi,
+                                    max_steps=10**9, seed=5)
+        s = oracle_mod.escape_steps(p, 0, 1000) * dt
+        tau_k = 1.0 / (wa / (2 * math.pi) * lam / wb * math.exp(-ratio))
+        assert s.mean() == pytest.approx(tau_k, rel=0.15)
+        means[ratio] = s.mean()
+    slope = math.log(means[5.0] / means[4.0]) / (5.0 - 4.0)  # in units of dU
+    assert slope == pytest.approx(1.0, abs=0.12)
+
+
+# ---------------------------------------------------------------------------
+# Numbers printed by the paper
+
+
+def _golden():
+    with open(os.path.join(HERE, "golden", "paper_values.json")) as f:
+        return json.load(f)
+
+
+def test_barrier_height_matches_paper_value():
+    # the Arrhenius figure quotes Delta U = 0.0342 at gamma = 0.5 with the
+    # printed amplitude 0.05: 0.05 * 2[sqrt(1-g^2) - g arccos g]
+    a = _golden()["arrhenius_fig"]
+    assert a["amplitude_as_printed"] * dU(a["gamma"]) == pytest.approx(a["delta_U_theory"],
+                                                                      abs=5e-5)
+
+
+def test_normalized_units_match_paper_device():
+    # time unit hbar/E_C, E_C = (2e)^2/C, V0 = E_J/E_C with E_J = hbar Ic/(2e);
+    # the paper states h = 1e-4 is about 2e-4 of the plasma period 2 pi/sqrt(V0)
+    # and that the bias step is about 1e-12 per step at a 200 Hz sweep
+    d = _golden()["li07_fig"]
+    hbar, e = 1.054571817e-34, 1.602176634e-19
+    EC = (2 * e) ** 2 / d["C_farad"]
+    EJ = hbar * d["Ic_ampere"] / (2 * e)
+    V0 = EJ / EC
+    assert 150 < V0 < 300
+    ratio = d["h"] / (2 * math.pi / math.sqrt(V0))
+    assert ratio == pytest.approx(d["h_over_period_about"], rel=0.3)
+    t_unit = hbar / EC
+    bias_step = d["sweep_hz"] * t_unit * d["h"]
+    assert 0.5 * d["bias_step_about"] < bias_step < 3.0 * d["bias_step_about"]
+
+
+# ---------------------------------------------------------------------------
+# Brute force: an independent 50-digit re-implementation (pure Python integers
+# for the generator, mpmath for the arithmetic) gives the same escape steps.
+
+
+def _philox_py(ctr, key):
+    M = 0xFFFFFFFF
+    x = list(ctr)
+    k0, k1 = key
+    for _ in range(10):
+        p0 = 0xD2511F53 * x[0]
+        p1 = 0xCD9E8D57 * x[2]
+        x = [((p1 >> 32) ^ x[1] ^ k0) & M, p1 & M, ((p0 >> 32) ^ x[3] ^ k1) & M, p0 & M]
+        k0 = (k0 + 0x9E3779B9) & M
+        k1 = (k1 + 0xBB67AE85) & M
+    return x
+
+
+def _brute_escape(p, replica, mp):
+    mp.mp.dps = 50
+    seed = p["seed"]
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    alpha, T, V0, dt = (mp.mpf(p[k]) for k in ("alpha", "T", "V0", "dt"))
+    sigma = mp.sqrt(2 * alpha * T * dt)
+    phi, v, th = mp.mpf(p["phi0"]), mp.mpf(p["v0"]), mp.mpf(p["threshold"])
+    g = mp.mpf(p["gamma0"])
+    near = False
+    z = None
+    for k in range(1, p["max_steps"] + 1):
+        j, q = divmod(k - 1, 4)
+        if q == 0:
+            w = _philox_py([j & 0xFFFFFFFF, j >> 32, replica & 0xFFFFFFFF, replica >> 32], key)
+            u = [(mp.mpf(x) + mp.mpf(0.5)) / mp.mpf(2) ** 32 for x in w]
+            z = []
+            for a, b in ((u[0], u[1]), (u[2], u[3])):
+                r = mp.sqrt(-2 * mp.log(a))
+                z += [r * mp.cos(2 * mp.pi * b), r * mp.sin(2 * mp.pi * b)]
+        phi, v = phi + dt * v, v + dt * (-alpha * v - V0 * mp.sin(phi) + V0 * g) + sigma * z[q]
+        if abs(phi - th) < mp.mpf("1e-9"):
+            near = True
+        if phi > th:
+            return k, near
+    return -1, near
+
+
+def test_brute_force_tiny(oracle_mod):
+    mp = pytest.importorskip("mpmath")
+    phi0 = math.asin(0.95)
+    p = dict(model=0, alpha=0.1, T=0.02, V0=1.0, gamma0=0.95, ramp=0.0, dt=0.01,
+             phi0=phi0, v0=0.0, threshold=phi0 + 2 * math.pi, max_steps=3000, seed=1)
+    op = oracle_mod.OracleParams(**p)
+    got = oracle_mod.escape_steps(op, 0, 12)
+    escaped = 0
+    for r in range(12):
+        k, near = _brute_escape(p, r, mp)
+        if not near:
+            assert k == got[r], r
+        escaped += k > 0
+    assert escaped >= 1  # at least one replica exercises the escape branch
+
+
+# ---------------------------------------------------------------------------
+# Histogram and moments: exact integer definitions, checked by brute force.
+
+
+def test_histogram_and_moments_brute_force(oracle_mod):
+    rng = np.random.Generator(np.random.PCG64(5))
+    k_hist, n_bins, dt = 1000, 7, 0.25
+    steps = rng.integers(1, 1300, size=5000).astype(np.int64)
+    steps[::17] = -1
+    steps[:4] = [1, k_hist, k_hist + 1, -1]
+    hist, m = oracle_mod.histogram(steps, n_bins, k_hist, dt)
+    ref = np.zeros(n_bins, dtype=np.int64)
+    for k in steps:
+        if 1 <= k <= k_hist:
+            # bin b covers the steps k with b*k_hist <= (k-1)*n_bins < (b+1)*k_hist
+            b = next(b for b in range(n_bins) if b * k_hist <= (k - 1) * n_bins < (b + 1) * k_hist)
+            ref[b] += 1
+    assert hist.tolist() == ref.tolist()
+    esc = [int(k) for k in steps if k >= 1]
+    assert m["n_escaped"] == len(esc)
+    assert m["n_censored"] == int((steps < 1).sum())
+    assert m["n_overflow"] == sum(1 for k in esc if k > k_hist)
+    assert m["sum_k"] == sum(esc)
+    assert m["sum_k2"] == sum(k * k for k in esc)
+    mean = sum(esc) / len(esc)
+    assert m["mean_t"] == pytest.approx(dt * mean, rel=1e-14)
+    sd = np.std(np.array(esc, dtype=np.float64), ddof=1)
+    assert m["se_t"] == pytest.approx(dt * sd / math.sqrt(len(esc)), rel=1e-9)
+
+
+def test_moments_128bit(oracle_mod):
+    # sum of k^2 beyond 2^64 is carried into the high word
+    k = 2**40
+    steps = np.full(1000, k, dtype=np.int64)
+    _, m = oracle_mod.histogram(steps, 4, 2**41, 1.0)
+    assert m["sum_k2"] == 1000 * k * k
+    assert m["sum_k2_hi"] > 0
+    assert m["se_t"] == 0.0
