@@ -1,0 +1,238 @@
+/*
+ * fpt.h -- C ABI of the MI355X (gfx950) first-passage-time library.
+ *
+ * The library integrates many independent Langevin replicas of a Josephson
+ * junction in a tilted washboard potential, each until its phase crosses a
+ * threshold, records every first-passage step and bins the steps into
+ * escape-time / switching-current histograms.  The method is that of
+ * Pierro, Troiano, Mejuto, Filatrella, "Stochastic first passage time
+ * accelerated with CUDA" (arXiv:1802.05065):
+ *   - Eq. (10): phi'' + beta phi' = V0 (-sin phi + gamma + gamma_N), with the
+ *     noise strength of Eqs. (11)-(12), D = beta theta (Eq. (9));
+ *   - Algorithm 1 (EscapeTime): explicit Euler-Maruyama from
+ *     (phi0, v0) = (arcsin gamma, 0) until phi > pi - phi0, recording k*h or
+ *     -1 after klim steps;
+ *   - Algorithm 3 (SwitchingCurrent): the same with the bias ramped by
+ *     delta-gamma per step, recording the bias at the crossing;
+ *   - Sect. III.B: one realization per thread, a finished thread takes the
+ *     next job (the streaming figure), the escape times land in an array.
+ *
+ * Conventions shared by every call:
+ *   - Units are the paper's normalized units with the damping called alpha
+ *     (beta in Eq. (10)) and the temperature called T (theta in Eq. (9)).
+ *     Underdamped step k (k = 1, 2, ...), both updates from step k-1 values:
+ *       phi_k = phi_{k-1} + dt v_{k-1}
+ *       v_k   = v_{k-1} + dt (-alpha v_{k-1} - V0 sin phi_{k-1} + V0 gamma_k)
+ *               + sqrt(2 alpha T dt) r_k
+ *     Overdamped (first-order analogue, Sect. II.B):
+ *       phi_k = phi_{k-1} + dt (-V0 sin phi_{k-1} + gamma_k) + sqrt(2 T dt) r_k
+ *     with gamma_k = gamma0 + ramp*dt*k evaluated in FP64 from the integer k.
+ *   - r_k is standard normal number (k-1) mod 4 of block (k-1) div 4 of the
+ *     replica: Philox4x32-10 with key = seed and counter = (block, replica
+ *     index within its parameter set), mapped u = (x + 1/2) 2^-32 and
+ *     Box-Muller (cos, sin) on word pairs (0,1) and (2,3).  Results therefore
+ *     depend only on (parameters, seed, replica index), never on the lane,
+ *     launch shape, tuning or on other sets running at the same time.
+ *   - Escape: the first k in [1, max_steps] with phi_k > threshold (strict).
+ *     None: the replica is censored and recorded as -1.
+ *   - Escape steps are int64; time = k*dt and switching bias = gamma_k are
+ *     derived by the caller in FP64.
+ *   - Device pointers are plain HIP device addresses (e.g. torch tensors'
+ *     data_ptr()); streams are hipStream_t passed as void* (NULL = default).
+ *     The caller owns every buffer it passes; the library never frees them.
+ *   - Errors are negative fpt_status values; fpt_last_error() returns the
+ *     calling thread's last message.  No call aborts or throws across the ABI.
+ */
+#ifndef FPT_H
+#define FPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FPT_API_VERSION 1
+#define FPT_MAX_BINS 4096
+
+typedef enum {
+  FPT_OK = 0,
+  FPT_PENDING = 1,      /* fpt_poll: job admitted or queued, not finished */
+  FPT_E_INVAL = -1,     /* bad argument; nothing was launched */
+  FPT_E_NOMEM = -2,     /* workspace / pool too small for the request */
+  FPT_E_DEVICE = -3,    /* a HIP call failed (message names it) */
+  FPT_E_BUSY = -4,      /* server queue full */
+  FPT_E_NOTFOUND = -5,  /* unknown job id */
+  FPT_E_STATE = -6      /* call out of order (e.g. histogram before simulate) */
+} fpt_status;
+
+typedef enum { FPT_UNDERDAMPED = 0, FPT_OVERDAMPED = 1 } fpt_model;
+
+/* FPT_FP64: every replica operation in FP64 (the plain path).
+ * FPT_FP32C: replica state in FP32 with Kahan-compensated phase accumulation;
+ * FP64 is kept for gamma_k from the exact integer step and for the threshold
+ * test near the threshold.  The same Philox words feed both. */
+typedef enum { FPT_FP64 = 0, FPT_FP32C = 1 } fpt_precision;
+
+/* FPT_SCHED_REFILL: persistent lanes; a lane whose replica escaped or was
+ * censored takes the next undrawn replica (the paper's "assign a new job to
+ * the processor that has just completed", done on the device).
+ * FPT_SCHED_ONE_PER_LANE: replica i is bound to lane i for its whole run
+ * (Algorithm 1's one-realization-per-thread launch). */
+typedef enum { FPT_SCHED_REFILL = 0, FPT_SCHED_ONE_PER_LANE = 1 } fpt_schedule;
+
+/* One parameter set ("job").  NaN phi0 / v0 / threshold select Algorithm 1's
+ * defaults arcsin(gamma0), 0 and pi - phi0. */
+typedef struct fpt_params {
+  int32_t model;        /* fpt_model */
+  int32_t n_bins;       /* histogram bins, 1..FPT_MAX_BINS */
+  double alpha;         /* damping (underdamped), >= 0 */
+  double T;             /* temperature, >= 0 (T = 0: noise-free) */
+  double V0;            /* potential amplitude (1 in plasma units) */
+  double gamma0;        /* bias at t = 0 */
+  double ramp;          /* d gamma / dt per unit time (0: fixed bias) */
+  double dt;            /* Euler step h, > 0 */
+  double phi0, v0;      /* initial state (NaN: defaults) */
+  double threshold;     /* escape when phi > threshold (NaN: pi - phi0) */
+  int64_t max_steps;    /* klim, >= 1 */
+  int64_t n_replicas;   /* >= 0 */
+  int64_t hist_k_max;   /* bins cover steps [1, hist_k_max]; 0: max_steps.
+                           bin(k) = ((k-1) n_bins) div hist_k_max;
+                           k > hist_k_max counts as overflow */
+  uint64_t seed;        /* Philox key */
+} fpt_params;
+
+/* Launch tuning.  Zero fields are filled by the autotuner (cached per GPU
+ * architecture, precision, model and set-count bucket). */
+typedef struct fpt_tuning {
+  int32_t schedule;          /* fpt_schedule */
+  int32_t replicas_per_lane; /* 1 or 2 (0: autotune) */
+  int32_t waves_per_simd;    /* 1..8 resident waves per SIMD (0: autotune) */
+  int32_t steps_per_launch;  /* multiple of 4 (0: autotune) */
+  int32_t use_graph;         /* 1: replay launches through a captured hipGraph */
+  int32_t reserved[3];
+} fpt_tuning;
+
+/* Per-set results.  Moments are over escaped replicas; times in units of t. */
+typedef struct fpt_moments {
+  uint64_t n_escaped, n_censored, n_overflow;
+  uint64_t sum_k;                 /* sum of escape steps */
+  uint64_t sum_k2_lo, sum_k2_hi;  /* 128-bit sum of squared escape steps */
+  double mean_t, se_t;            /* dt*mean(k), dt*stddev(k)/sqrt(n) */
+} fpt_moments;
+
+typedef struct fpt_run_stats {
+  uint64_t replica_steps;     /* sum of k over escaped + max_steps per censored */
+  uint64_t lane_steps;        /* lane-steps issued (idle lanes included) */
+  int64_t n_launches;         /* integrator launches of the last simulate */
+  double kernel_ms;           /* sum of their durations (HIP events) */
+  double wall_ms;             /* fpt_simulate entry to last launch done */
+  fpt_tuning tuning;          /* tuning actually used */
+} fpt_run_stats;
+
+typedef struct fpt_plan_s* fpt_plan_t;
+typedef struct fpt_server_s* fpt_server_t;
+
+/* ---- plans: a fixed batch of parameter sets ------------------------------ */
+
+/* Validate n_sets parameter sets (all of one model) and derive the per-set
+ * constants of Algorithm 1 / 3's preamble: sigma = sqrt(2 alpha T dt)
+ * (overdamped sqrt(2 T dt)), delta-gamma = ramp*dt, phi0, v0, threshold.
+ * tuning may be NULL (all fields autotuned).  Host-only; no device memory.
+ * Errors: FPT_E_INVAL (message names the set and field). */
+fpt_status fpt_plan(const fpt_params* sets, int32_t n_sets, int32_t precision,
+                    const fpt_tuning* tuning, fpt_plan_t* out);
+
+/* Bytes of device workspace fpt_simulate needs for this plan (caller
+ * allocates, 256-byte aligned, and may reuse it across calls). */
+fpt_status fpt_plan_workspace(fpt_plan_t plan, size_t* bytes);
+
+/* Run every replica of every set.  Asynchronous on `stream`.
+ *   workspace : device, >= fpt_plan_workspace bytes
+ *   out_steps : host array of n_sets device pointers (int64[n_replicas] each,
+ *               entries may be NULL), or NULL: escape step per replica, -1 if
+ *               censored
+ *   out_hist  : device uint64[sum of n_bins], sets in plan order, or NULL
+ *               (then kept in the workspace); zeroed by the call
+ * Results are identical for every tuning.  Errors: FPT_E_INVAL, FPT_E_DEVICE. */
+fpt_status fpt_simulate(fpt_plan_t plan, void* workspace,
+                        int64_t* const* out_steps, uint64_t* out_hist,
+                        void* stream);
+
+/* Copy set `set`'s histogram (n_bins counts) and moments of the last
+ * fpt_simulate to host memory; synchronizes that call's stream.  Either
+ * pointer may be NULL.  Errors: FPT_E_STATE before a simulate. */
+fpt_status fpt_histogram(fpt_plan_t plan, int32_t set, uint64_t* host_counts,
+                         fpt_moments* host_m);
+
+/* Counters and timing of the last fpt_simulate (synchronizes). */
+fpt_status fpt_plan_stats(fpt_plan_t plan, fpt_run_stats* out);
+
+void fpt_plan_destroy(fpt_plan_t plan);
+
+/* ---- serving: jobs admitted continuously -------------------------------- */
+
+/* A request loop on its own host thread owns `stream` and the caller's
+ * device pool (`pool_bytes` at `device_pool`, which must stay allocated until
+ * fpt_server_destroy).  Jobs are admitted as set slots and pool memory free
+ * up; their replicas share the resident persistent lanes with the jobs
+ * already running.  Errors: FPT_E_NOMEM if the pool cannot hold the fixed
+ * lane state. */
+fpt_status fpt_server_create(void* device_pool, size_t pool_bytes,
+                             int32_t precision, int32_t model,
+                             const fpt_tuning* tuning, void* stream,
+                             fpt_server_t* out);
+
+/* Queue one job (non-blocking, thread-safe).  FPT_E_NOMEM if the job could
+ * never fit the pool, FPT_E_INVAL for bad parameters, FPT_E_BUSY if the
+ * queue is full. */
+fpt_status fpt_submit(fpt_server_t server, const fpt_params* params,
+                      uint64_t* job_id);
+
+/* FPT_PENDING while queued or running; FPT_OK once finished, filling
+ * host_counts (n_bins), moments and the submit-to-finish latency (any may
+ * be NULL).  A finished job is forgotten after its first FPT_OK. */
+fpt_status fpt_poll(fpt_server_t server, uint64_t job_id,
+                    uint64_t* host_counts, fpt_moments* host_m,
+                    double* latency_s);
+
+typedef struct fpt_server_stats {
+  uint64_t submitted, admitted, finished, queued, running;
+  uint64_t replica_steps;   /* of finished jobs */
+  int64_t n_launches;
+  double busy_s;            /* time with at least one job running */
+} fpt_server_stats;
+
+fpt_status fpt_server_stats_get(fpt_server_t server, fpt_server_stats* out);
+
+/* Stops the loop after the running launch, drops unfinished jobs. */
+void fpt_server_destroy(fpt_server_t server);
+
+/* ---- diagnostics (same device code as the integrator) ------------------- */
+
+/* Philox words of replicas [replica0, replica0+n_rep) x blocks
+ * [block0, block0+n_blk): out[((r*n_blk)+b)*4 + w], device uint32. */
+fpt_status fpt_rng_words(uint64_t seed, uint64_t replica0, int64_t n_rep,
+                         uint64_t block0, int64_t n_blk, uint32_t* out,
+                         void* stream);
+
+/* The four normals of the same blocks, as the integrator of `precision`
+ * computes them: out is device double (FPT_FP64) or float (FPT_FP32C). */
+fpt_status fpt_normals(uint64_t seed, uint64_t replica0, int64_t n_rep,
+                       uint64_t block0, int64_t n_blk, int32_t precision,
+                       void* out, void* stream);
+
+/* State (phi, v) after each of n_steps steps of one replica, no threshold:
+ * out_phi / out_v device double[n_steps] (FP32C: phi_hi - c and v widened). */
+fpt_status fpt_trajectory(const fpt_params* params, uint64_t replica,
+                          int64_t n_steps, int32_t precision, double* out_phi,
+                          double* out_v, void* stream);
+
+const char* fpt_last_error(void);
+int32_t fpt_api_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPT_H */

@@ -1,0 +1,716 @@
+// kernels.hip -- gfx950 kernels of the first-passage-time library.
+//
+// The integrator is one kernel template: one wavefront lane holds R replicas
+// ("slots") in registers and advances them in blocks of 4 Euler steps (one
+// Philox call feeds the 4 normals of a block).  A launch runs at most
+// `blocks` blocks and leaves every slot's state resident in device memory, so
+// long runs are split into launches and a server can add work between them.
+//
+// Scheduling (Sect. III.B, the streaming figure): with `refill` set, a slot
+// whose replica escaped or was censored takes the next undrawn replica from a
+// global cursor.  The wavefront draws for all its free slots with one atomic
+// (ballot + popcount + mbcnt), so uneven escape times do not idle lanes.
+// Without `refill` each slot keeps the replica assigned at the start
+// (one realization per thread, Algorithm 1's launch).
+//
+// Results (the escape-time / switching-current histograms of Sect. II.B and
+// IV.B): finished replicas write their step to the caller's array, then add
+// to a per-workgroup LDS hash table of (set, bin) counts and of per-set
+// integer moments; lanes of a wavefront that finish in the same block with
+// the same (set, bin) are merged first.  At the end of a launch each
+// workgroup adds its LDS tables to the global histogram / moments with one
+// atomic per occupied entry.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_math.hpp"
+#include "internal.hpp"
+#include "launch.hpp"
+
+namespace fpt {
+
+// ---------------------------------------------------------------------------
+// Slot state
+
+template <bool FP64>
+struct Slot;
+
+template <>
+struct Slot<true> {
+  uint32_t set;
+  uint64_t idx, j;
+  double kd;  // 4 j as a double (exact below 2^53)
+  double phi, v;
+  float c;    // unused in FP64
+  ParF64 p;
+  uint32_t k0, k1;
+  uint64_t jmax;
+};
+
+template <>
+struct Slot<false> {
+  uint32_t set;
+  uint64_t idx, j;
+  double kd;
+  float phi, v;
+  float c;
+  ParF32 p;
+  uint32_t k0, k1;
+  uint64_t jmax;
+};
+
+template <bool FP64>
+__device__ __forceinline__ void load_params(Slot<FP64>& s, const SetDev& sd) {
+  if constexpr (FP64) {
+    s.p = load_par_f64(sd);
+  } else {
+    s.p = load_par_f32(sd);
+  }
+  s.k0 = (uint32_t)sd.seed;
+  s.k1 = (uint32_t)(sd.seed >> 32);
+  s.jmax = sd.jmax;
+}
+
+template <bool FP64>
+__device__ __forceinline__ void start_replica(Slot<FP64>& s, uint32_t set,
+                                              uint64_t idx, const SetDev& sd) {
+  s.set = set;
+  s.idx = idx;
+  s.j = 0;
+  s.kd = 0.0;
+  if constexpr (FP64) {
+    s.phi = sd.phi0;
+    s.v = sd.v0;
+    s.c = 0.0f;
+  } else {
+    s.phi = sd.phi0_f;
+    s.c = sd.c0_f;
+    s.v = sd.v0_f;
+  }
+}
+
+// Resident-state encoding: st_phi holds the FP64 phase, or the FP32 pair
+// (phi, c) in the low / high word; st_v the FP64 or FP32 velocity.
+template <bool FP64>
+__device__ __forceinline__ void store_slot(const SliceArgs& a, uint64_t slot,
+                                           const Slot<FP64>& s) {
+  a.st_set[slot] = s.set;
+  if (s.set == kInactive) return;
+  a.st_idx[slot] = s.idx;
+  a.st_j[slot] = s.j;
+  if constexpr (FP64) {
+    a.st_phi[slot] = (unsigned long long)__double_as_longlong(s.phi);
+    a.st_v[slot] = (unsigned long long)__double_as_longlong(s.v);
+  } else {
+    a.st_phi[slot] = (unsigned long long)__float_as_uint(s.phi) |
+                     ((unsigned long long)__float_as_uint(s.c) << 32);
+    a.st_v[slot] = (unsigned long long)__float_as_uint(s.v);
+  }
+}
+
+template <bool FP64>
+__device__ __forceinline__ void restore_slot(const SliceArgs& a, uint64_t slot,
+                                             Slot<FP64>& s) {
+  s.set = a.st_set[slot];
+  s.idx = 0;
+  s.j = 0;
+  s.kd = 0.0;
+  s.phi = 0;
+  s.v = 0;
+  s.c = 0.0f;
+  if (s.set == kInactive) return;
+  s.idx = a.st_idx[slot];
+  s.j = a.st_j[slot];
+  s.kd = 4.0 * (double)s.j;
+  const unsigned long long ph = a.st_phi[slot];
+  const unsigned long long vv = a.st_v[slot];
+  if constexpr (FP64) {
+    s.phi = __longlong_as_double((long long)ph);
+    s.v = __longlong_as_double((long long)vv);
+    s.c = 0.0f;
+  } else {
+    s.phi = __uint_as_float((uint32_t)ph);
+    s.c = __uint_as_float((uint32_t)(ph >> 32));
+    s.v = __uint_as_float((uint32_t)vv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t x, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// 128-bit accumulation with two 64-bit atomics: the carry of the low word is
+// known exactly from the value the atomic returns.
+__device__ __forceinline__ void atomic_add_u128(unsigned long long* lo,
+                                                unsigned long long* hi,
+                                                unsigned long long add_lo,
+                                                unsigned long long add_hi) {
+  const unsigned long long old = atomicAdd(lo, add_lo);
+  const unsigned long long carry = (old + add_lo < old) ? 1ull : 0ull;
+  if (add_hi + carry) atomicAdd(hi, add_hi + carry);
+}
+
+// ---------------------------------------------------------------------------
+// LDS result tables
+
+struct LdsTables {
+  uint32_t h_key[kHistSlots];
+  uint32_t h_cnt[kHistSlots];
+  uint32_t m_key[kMomSlots];
+  unsigned long long m_val[kMomSlots][6];  // esc, cens, over, sum_k, k2 lo, hi
+};
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  return (x * 2654435761u) >> 16;
+}
+
+// Per-set output description needed when a replica finishes.
+struct SetOut {
+  int64_t* out_steps;
+  int64_t k_hist;
+  uint64_t hist_off;
+  uint32_t n_bins;
+};
+
+__device__ __forceinline__ SetOut set_out(const SetDev& s) {
+  return SetOut{s.out_steps, s.k_hist, s.hist_off, s.n_bins};
+}
+
+__device__ void hist_add(LdsTables& t, const SliceArgs& a, uint32_t key,
+                         uint32_t count, uint64_t global_index) {
+  uint32_t h = hash32(key) & (kHistSlots - 1);
+#pragma unroll 1
+  for (int probe = 0; probe < kProbes; ++probe) {
+    const uint32_t prev = atomicCAS(&t.h_key[h], kEmpty, key);
+    if (prev == kEmpty || prev == key) {
+      atomicAdd(&t.h_cnt[h], count);
+      return;
+    }
+    h = (h + 1) & (kHistSlots - 1);
+  }
+  atomicAdd(&a.hist[global_index], (unsigned long long)count);
+}
+
+__device__ void mom_add(LdsTables& t, const SliceArgs& a, uint32_t set,
+                        int64_t k, bool overflow) {
+  const unsigned long long esc = k > 0 ? 1ull : 0ull;
+  const unsigned long long cens = 1ull - esc;
+  const unsigned long long over = overflow ? 1ull : 0ull;
+  const unsigned long long kk = k > 0 ? (unsigned long long)k : 0ull;
+  const unsigned long long k2lo = kk * kk;
+  const unsigned long long k2hi = __umul64hi(kk, kk);
+  uint32_t h = hash32(set) & (kMomSlots - 1);
+#pragma unroll 1
+  for (int probe = 0; probe < kMomSlots; ++probe) {
+    const uint32_t prev = atomicCAS(&t.m_key[h], kEmpty, set);
+    if (prev == kEmpty || prev == set) {
+      unsigned long long* v = t.m_val[h];
+      if (esc) atomicAdd(&v[0], 1ull);
+      if (cens) atomicAdd(&v[1], 1ull);
+      if (over) atomicAdd(&v[2], 1ull);
+      if (kk) {
+        atomicAdd(&v[3], kk);
+        atomic_add_u128(&v[4], &v[5], k2lo, k2hi);
+      }
+      return;
+    }
+    h = (h + 1) & (kMomSlots - 1);
+  }
+  MomDev* m = &a.mom[set];
+  if (esc) atomicAdd(&m->n_esc, 1ull);
+  if (cens) atomicAdd(&m->n_cens, 1ull);
+  if (over) atomicAdd(&m->n_over, 1ull);
+  if (kk) {
+    atomicAdd(&m->sum_k, kk);
+    atomic_add_u128(&m->sum_k2_lo, &m->sum_k2_hi, k2lo, k2hi);
+  }
+  atomicAdd(&a.ctr->done, 1ull);
+}
+
+// Record finished replicas of one slot across the wavefront.  `fin` lanes
+// have finished with step k (k = -1: censored).
+__device__ void record_finished(LdsTables& t, const SliceArgs& a, bool fin,
+                                uint32_t set, uint64_t idx, int64_t k) {
+  SetOut so{nullptr, 1, 0, 1};
+  uint32_t key = kEmpty;
+  bool in_hist = false;
+  if (fin) {
+    so = set_out(a.sets[set]);
+    if (so.out_steps) so.out_steps[idx] = k;
+    if (k > 0 && k <= so.k_hist) {
+      const uint64_t bin =
+          (uint64_t)((k - 1) * (int64_t)so.n_bins) / (uint64_t)so.k_hist;
+      key = (set << kBinBits) | (uint32_t)bin;
+      in_hist = true;
+    }
+    mom_add(t, a, set, k, k > so.k_hist);
+  }
+  // Wavefront merge: one LDS add per distinct (set, bin) among the lanes.
+  uint64_t pending = __ballot(in_hist);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t lkey = __builtin_amdgcn_readlane((int)key, leader);
+    const uint64_t same = __ballot(in_hist && key == lkey);
+    if (lane_id() == (uint32_t)leader) {
+      const uint32_t bin = key & ((1u << kBinBits) - 1);
+      hist_add(t, a, key, (uint32_t)__popcll(same), so.hist_off + bin);
+    }
+    pending &= ~same;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Drawing replicas from the work queue.
+
+// Grants up to `want` consecutive flat indices to the wavefront; returns the
+// first in *base and the number granted.  Plans: plain atomicAdd (indices at
+// or past `total` are simply empty).  Server: the cursor never passes
+// `total`, so work appended later is not skipped.
+__device__ __forceinline__ uint32_t draw(const SliceArgs& a, uint32_t want,
+                                         unsigned long long* base) {
+  if (!a.clamp) {
+    const unsigned long long b = atomicAdd(&a.ctr->cursor, (unsigned long long)want);
+    *base = b;
+    if (b >= a.total) return 0;
+    const unsigned long long avail = a.total - b;
+    return avail < want ? (uint32_t)avail : want;
+  }
+  unsigned long long old = atomicAdd(&a.ctr->cursor, 0ull);
+  for (;;) {
+    const unsigned long long avail = old < a.total ? a.total - old : 0ull;
+    const uint32_t take = avail < want ? (uint32_t)avail : want;
+    if (take == 0) {
+      *base = old;
+      return 0;
+    }
+    const unsigned long long prev = atomicCAS(&a.ctr->cursor, old, old + take);
+    if (prev == old) {
+      *base = old;
+      return take;
+    }
+    old = prev;
+  }
+}
+
+// Flat index -> (set, replica).  False for padding inside a chunk.
+__device__ __forceinline__ bool map_flat(const SliceArgs& a, uint64_t flat,
+                                         uint32_t* set, uint64_t* idx) {
+  if (a.chunks == nullptr) {
+    *set = 0;
+    *idx = flat;
+    return true;
+  }
+  const Chunk ch = a.chunks[(flat / kChunk) & a.chunk_mask];
+  const uint32_t off = (uint32_t)(flat % kChunk);
+  *set = ch.set;
+  *idx = ch.first + off;
+  return off < ch.count;
+}
+
+// ---------------------------------------------------------------------------
+// The integrator launch.
+
+template <bool FP64, int MODEL, int R, bool MULTI>
+__global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
+  __shared__ LdsTables tab;
+  for (int i = threadIdx.x; i < kHistSlots; i += kBlockThreads) {
+    tab.h_key[i] = kEmpty;
+    tab.h_cnt[i] = 0;
+  }
+  for (int i = threadIdx.x; i < kMomSlots; i += kBlockThreads) {
+    tab.m_key[i] = kEmpty;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) tab.m_val[i][f] = 0ull;
+  }
+  __syncthreads();
+
+  const uint64_t lane_g = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  const uint32_t lane = lane_id();
+
+  // Uniform parameters of a single-set plan (scalar registers).
+  Slot<FP64> uni;
+  load_params(uni, a.sets[0]);
+
+  Slot<FP64> s[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    restore_slot(a, (uint64_t)r * a.n_lanes + lane_g, s[r]);
+    if (MULTI && s[r].set != kInactive) load_params(s[r], a.sets[s[r].set]);
+  }
+
+  bool starved = false;
+  uint32_t blocks_run = 0;
+  for (int blk = 0; blk < a.blocks; ++blk) {
+    // ---- refill free slots
+    if (a.refill && !starved) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool free_slot = s[r].set == kInactive;
+        const uint64_t need = __ballot(free_slot);
+        if (need) {
+          const uint32_t want = (uint32_t)__popcll(need);
+          const int leader = __ffsll((unsigned long long)need) - 1;
+          unsigned long long base = 0;
+          uint32_t got = 0;
+          if (lane == (uint32_t)leader) got = draw(a, want, &base);
+          got = __builtin_amdgcn_readlane((int)got, leader);
+          base = read_lane_u64(base, leader);
+          if (got < want) starved = true;
+          if (free_slot) {
+            const uint32_t rk = rank_in(need);
+            uint32_t set;
+            uint64_t idx;
+            if (rk < got && map_flat(a, base + rk, &set, &idx)) {
+              const SetDev& sd = a.sets[set];
+              start_replica(s[r], set, idx, sd);
+              if (MULTI) load_params(s[r], sd);
+            }
+          }
+        }
+      }
+    }
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) any |= s[r].set != kInactive;
+    if (__ballot(any) == 0) break;
+    ++blocks_run;
+
+    // ---- 4 Euler steps per slot
+    uint64_t esc[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      Slot<FP64>& sl = s[r];
+      const auto& p = MULTI ? sl.p : uni.p;
+      const uint32_t k0 = MULTI ? sl.k0 : uni.k0;
+      const uint32_t k1 = MULTI ? sl.k1 : uni.k1;
+      const Words w = philox4x32_10((uint32_t)sl.j, (uint32_t)(sl.j >> 32),
+                                    (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32),
+                                    k0, k1);
+      if constexpr (FP64) {
+        double z[4];
+        normals_f64(w, z);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double kd = sl.kd + (double)(q + 1);
+          if constexpr (MODEL == FPT_UNDERDAMPED) {
+            step_f64_under(p, kd, z[q], sl.phi, sl.v);
+          } else {
+            step_f64_over(p, kd, z[q], sl.phi);
+          }
+          esc[r][q] = __ballot(sl.phi > p.th);
+        }
+      } else {
+        float z[4];
+        normals_f32(w, z);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double kd = sl.kd + (double)(q + 1);
+          if constexpr (MODEL == FPT_UNDERDAMPED) {
+            step_f32_under(p, kd, z[q], sl.phi, sl.c, sl.v);
+          } else {
+            step_f32_over(p, kd, z[q], sl.phi, sl.c);
+          }
+          const uint64_t near = __ballot(sl.phi > p.th_near);
+          esc[r][q] = near ? __ballot(above_f64(sl.phi, sl.c, p.th)) : 0ull;
+        }
+      }
+    }
+
+    // ---- escapes, censoring, next block
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      Slot<FP64>& sl = s[r];
+      const bool active = sl.set != kInactive;
+      const uint64_t jmax = MULTI ? sl.jmax : uni.jmax;
+      const uint64_t act = __ballot(active);
+      const uint64_t crossed = (esc[r][0] | esc[r][1] | esc[r][2] | esc[r][3]) & act;
+      const uint64_t last = __ballot(active && sl.j >= jmax);
+      if (crossed | last) {
+        bool fin = false;
+        int64_t k = -1;
+        if (active) {
+          const uint64_t bit = 1ull << lane;
+          int q1 = 0;
+          if (esc[r][0] & bit) q1 = 1;
+          else if (esc[r][1] & bit) q1 = 2;
+          else if (esc[r][2] & bit) q1 = 3;
+          else if (esc[r][3] & bit) q1 = 4;
+          const int64_t kesc = q1 ? (int64_t)(4 * sl.j) + q1 : 0;
+          const int64_t max_steps = a.sets[MULTI ? sl.set : 0].max_steps;
+          if (q1 && kesc <= max_steps) {
+            fin = true;
+            k = kesc;
+          } else if (sl.j >= jmax) {
+            fin = true;
+            k = -1;
+          }
+        }
+        record_finished(tab, a, fin, sl.set, sl.idx, k);
+        if (fin) sl.set = kInactive;
+      }
+      sl.j += 1;
+      sl.kd += 4.0;
+    }
+  }
+
+  // ---- leave state resident, count issued lane-steps
+#pragma unroll
+  for (int r = 0; r < R; ++r) store_slot(a, (uint64_t)r * a.n_lanes + lane_g, s[r]);
+  if (lane == 0 && blocks_run)
+    atomicAdd(&a.ctr->lane_steps,
+              (unsigned long long)blocks_run * (unsigned long long)(kWave * R * 4));
+
+  // ---- one global pass over the workgroup's LDS tables
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHistSlots; i += kBlockThreads) {
+    const uint32_t key = tab.h_key[i];
+    if (key != kEmpty && tab.h_cnt[i]) {
+      const uint32_t set = key >> kBinBits;
+      const uint32_t bin = key & ((1u << kBinBits) - 1);
+      const uint64_t off = a.sets[set].hist_off;
+      atomicAdd(&a.hist[off + bin], (unsigned long long)tab.h_cnt[i]);
+    }
+  }
+  for (int i = threadIdx.x; i < kMomSlots; i += kBlockThreads) {
+    const uint32_t set = tab.m_key[i];
+    if (set == kEmpty) continue;
+    const unsigned long long* v = tab.m_val[i];
+    MomDev* m = &a.mom[set];
+    if (v[0]) atomicAdd(&m->n_esc, v[0]);
+    if (v[1]) atomicAdd(&m->n_cens, v[1]);
+    if (v[2]) atomicAdd(&m->n_over, v[2]);
+    if (v[3]) atomicAdd(&m->sum_k, v[3]);
+    if (v[4] | v[5]) atomic_add_u128(&m->sum_k2_lo, &m->sum_k2_hi, v[4], v[5]);
+    if (v[0] + v[1]) atomicAdd(&a.ctr->done, v[0] + v[1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Start of a run: slot i takes flat replica i (if any); all others are free.
+
+template <bool FP64>
+__global__ __launch_bounds__(kBlockThreads) void init_kernel(SliceArgs a,
+                                                             uint64_t n_slots,
+                                                             uint64_t n_assign) {
+  const uint64_t slot = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  if (slot >= n_slots) return;
+  Slot<FP64> s;
+  s.set = kInactive;
+  s.idx = 0;
+  s.j = 0;
+  s.kd = 0.0;
+  s.phi = 0;
+  s.v = 0;
+  s.c = 0.0f;
+  uint32_t set;
+  uint64_t idx;
+  if (slot < n_assign && map_flat(a, slot, &set, &idx)) {
+    start_replica(s, set, idx, a.sets[set]);
+  }
+  store_slot(a, slot, s);
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, uint64_t n,
+                                unsigned long long value) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: the same device functions as the integrator.
+
+__global__ void rng_words_kernel(uint64_t seed, uint64_t replica0, uint64_t n_rep,
+                                 uint64_t block0, uint64_t n_blk, uint32_t* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rep * n_blk) return;
+  const uint64_t r = i / n_blk, b = i % n_blk;
+  const Words w = replica_words(seed, replica0 + r, block0 + b);
+  out[4 * i + 0] = w.w0;
+  out[4 * i + 1] = w.w1;
+  out[4 * i + 2] = w.w2;
+  out[4 * i + 3] = w.w3;
+}
+
+template <bool FP64>
+__global__ void normals_kernel(uint64_t seed, uint64_t replica0, uint64_t n_rep,
+                               uint64_t block0, uint64_t n_blk, void* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rep * n_blk) return;
+  const uint64_t r = i / n_blk, b = i % n_blk;
+  const Words w = replica_words(seed, replica0 + r, block0 + b);
+  if constexpr (FP64) {
+    double z[4];
+    normals_f64(w, z);
+    for (int q = 0; q < 4; ++q) static_cast<double*>(out)[4 * i + q] = z[q];
+  } else {
+    float z[4];
+    normals_f32(w, z);
+    for (int q = 0; q < 4; ++q) static_cast<float*>(out)[4 * i + q] = z[q];
+  }
+}
+
+template <bool FP64, int MODEL>
+__global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
+                                  double* out_phi, double* out_v) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  Slot<FP64> s;
+  start_replica(s, 0, replica, sd);
+  load_params(s, sd);
+  for (int64_t k0 = 0; k0 < n_steps; k0 += 4) {
+    const Words w = replica_words(sd.seed, replica, s.j);
+    if constexpr (FP64) {
+      double z[4];
+      normals_f64(w, z);
+      for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
+        const double kd = s.kd + (double)(q + 1);
+        if constexpr (MODEL == FPT_UNDERDAMPED) {
+          step_f64_under(s.p, kd, z[q], s.phi, s.v);
+        } else {
+          step_f64_over(s.p, kd, z[q], s.phi);
+        }
+        out_phi[k0 + q] = s.phi;
+        out_v[k0 + q] = s.v;
+      }
+    } else {
+      float z[4];
+      normals_f32(w, z);
+      for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
+        const double kd = s.kd + (double)(q + 1);
+        if constexpr (MODEL == FPT_UNDERDAMPED) {
+          step_f32_under(s.p, kd, z[q], s.phi, s.c, s.v);
+        } else {
+          step_f32_over(s.p, kd, z[q], s.phi, s.c);
+        }
+        out_phi[k0 + q] = (double)s.phi - (double)s.c;
+        out_v[k0 + q] = (double)s.v;
+      }
+    }
+    s.j += 1;
+    s.kd += 4.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+
+template <bool FP64, int MODEL, int R, bool MULTI>
+static hipError_t launch_slice_t(const SliceArgs& a, uint32_t n_groups,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL((slice_kernel<FP64, MODEL, R, MULTI>), dim3(n_groups),
+                     dim3(kBlockThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+template <bool FP64, int MODEL, int R>
+static hipError_t launch_slice_m(bool multi, const SliceArgs& a, uint32_t n_groups,
+                                 hipStream_t st) {
+  return multi ? launch_slice_t<FP64, MODEL, R, true>(a, n_groups, st)
+               : launch_slice_t<FP64, MODEL, R, false>(a, n_groups, st);
+}
+
+template <bool FP64, int MODEL>
+static hipError_t launch_slice_r(int R, bool multi, const SliceArgs& a,
+                                 uint32_t n_groups, hipStream_t st) {
+  return R == 2 ? launch_slice_m<FP64, MODEL, 2>(multi, a, n_groups, st)
+                : launch_slice_m<FP64, MODEL, 1>(multi, a, n_groups, st);
+}
+
+hipError_t launch_slice(bool fp64, int model, int R, bool multi,
+                        const SliceArgs& a, uint32_t n_groups, hipStream_t st) {
+  if (fp64) {
+    return model == FPT_OVERDAMPED
+               ? launch_slice_r<true, FPT_OVERDAMPED>(R, multi, a, n_groups, st)
+               : launch_slice_r<true, FPT_UNDERDAMPED>(R, multi, a, n_groups, st);
+  }
+  return model == FPT_OVERDAMPED
+             ? launch_slice_r<false, FPT_OVERDAMPED>(R, multi, a, n_groups, st)
+             : launch_slice_r<false, FPT_UNDERDAMPED>(R, multi, a, n_groups, st);
+}
+
+hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,
+                       uint64_t n_assign, hipStream_t st) {
+  const uint32_t groups = (uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads);
+  if (groups == 0) return hipSuccess;
+  if (fp64) {
+    hipLaunchKernelGGL(init_kernel<true>, dim3(groups), dim3(kBlockThreads), 0, st,
+                       a, n_slots, n_assign);
+  } else {
+    hipLaunchKernelGGL(init_kernel<false>, dim3(groups), dim3(kBlockThreads), 0, st,
+                       a, n_slots, n_assign);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n,
+                           unsigned long long value, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint32_t groups = (uint32_t)((n + 255) / 256);
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(groups), dim3(256), 0, st, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_rng_words(uint64_t seed, uint64_t replica0, uint64_t n_rep,
+                            uint64_t block0, uint64_t n_blk, uint32_t* out,
+                            hipStream_t st) {
+  const uint64_t n = n_rep * n_blk;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(rng_words_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256),
+                     0, st, seed, replica0, n_rep, block0, n_blk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_normals(bool fp64, uint64_t seed, uint64_t replica0,
+                          uint64_t n_rep, uint64_t block0, uint64_t n_blk,
+                          void* out, hipStream_t st) {
+  const uint64_t n = n_rep * n_blk;
+  if (n == 0) return hipSuccess;
+  const dim3 g((uint32_t)((n + 255) / 256));
+  if (fp64) {
+    hipLaunchKernelGGL(normals_kernel<true>, g, dim3(256), 0, st, seed, replica0,
+                       n_rep, block0, n_blk, out);
+  } else {
+    hipLaunchKernelGGL(normals_kernel<false>, g, dim3(256), 0, st, seed, replica0,
+                       n_rep, block0, n_blk, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_trajectory(bool fp64, int model, const SetDev& sd,
+                             uint64_t replica, int64_t n_steps, double* out_phi,
+                             double* out_v, hipStream_t st) {
+  if (n_steps <= 0) return hipSuccess;
+  if (fp64) {
+    if (model == FPT_OVERDAMPED)
+      hipLaunchKernelGGL((trajectory_kernel<true, FPT_OVERDAMPED>), dim3(1), dim3(64),
+                         0, st, sd, replica, n_steps, out_phi, out_v);
+    else
+      hipLaunchKernelGGL((trajectory_kernel<true, FPT_UNDERDAMPED>), dim3(1), dim3(64),
+                         0, st, sd, replica, n_steps, out_phi, out_v);
+  } else {
+    if (model == FPT_OVERDAMPED)
+      hipLaunchKernelGGL((trajectory_kernel<false, FPT_OVERDAMPED>), dim3(1), dim3(64),
+                         0, st, sd, replica, n_steps, out_phi, out_v);
+    else
+      hipLaunchKernelGGL((trajectory_kernel<false, FPT_UNDERDAMPED>), dim3(1), dim3(64),
+                         0, st, sd, replica, n_steps, out_phi, out_v);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fpt

@@ -1,0 +1,28 @@
+// launch.hpp -- host entry points of the kernels in kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace fpt {
+
+hipError_t launch_slice(bool fp64, int model, int R, bool multi,
+                        const SliceArgs& a, uint32_t n_groups, hipStream_t st);
+hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,
+                       uint64_t n_assign, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n,
+                           unsigned long long value, hipStream_t st);
+hipError_t launch_rng_words(uint64_t seed, uint64_t replica0, uint64_t n_rep,
+                            uint64_t block0, uint64_t n_blk, uint32_t* out,
+                            hipStream_t st);
+hipError_t launch_normals(bool fp64, uint64_t seed, uint64_t replica0,
+                          uint64_t n_rep, uint64_t block0, uint64_t n_blk,
+                          void* out, hipStream_t st);
+hipError_t launch_trajectory(bool fp64, int model, const SetDev& sd,
+                             uint64_t replica, int64_t n_steps, double* out_phi,
+                             double* out_v, hipStream_t st);
+
+}  // namespace fpt

@@ -1,0 +1,69 @@
+// plan.hpp -- host-side state of an fpt_plan_t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace fpt {
+
+struct Plan {
+  std::vector<fpt_params> params;
+  std::vector<SetDev> sets;     // derived constants, hist offsets
+  std::vector<Chunk> chunks;    // multi-set work queue (64 replicas per entry)
+  int precision = FPT_FP64;
+  int model = FPT_UNDERDAMPED;
+  bool multi = false;
+  fpt_tuning tuning_req{};      // as given (zeros: autotune)
+  fpt_tuning tuning{};          // as used by the last simulate
+  uint64_t total_replicas = 0;
+  uint64_t total_flat = 0;      // size of the flat index space (with padding)
+  uint64_t hist_bins = 0;
+  int cus = 256;
+  std::string arch = "gfx950";
+
+  // workspace layout (byte offsets)
+  uint64_t max_slots = 0;
+  uint64_t off_sets = 0, off_chunks = 0, off_ctr = 0, off_mom = 0, off_hist = 0;
+  uint64_t off_st_phi = 0, off_st_v = 0, off_st_j = 0, off_st_idx = 0, off_st_set = 0;
+  uint64_t ws_bytes = 0;
+
+  // last run
+  uint64_t n_lanes = 0;
+  uint64_t* hist_dev = nullptr;
+  MomDev* ws_mom_ptr = nullptr;
+  hipStream_t stream = nullptr;
+  bool ran = false;
+  fpt_run_stats stats{};
+
+  // host resources (created lazily, on the first simulate)
+  Counters* h_ctr = nullptr;    // pinned
+  std::vector<hipEvent_t> events;
+  hipGraphExec_t graph_exec = nullptr;
+
+  ~Plan();
+  fpt_status layout();
+  SliceArgs slice_args(char* ws, uint64_t* hist, uint64_t n_lanes) const;
+  uint64_t lanes_for(const fpt_tuning& t) const;
+  uint64_t launch_bound(uint64_t n_slots, int blocks) const;
+  fpt_status ensure_host_resources(size_t n_events);
+  fpt_status upload_sets(char* ws, const std::vector<SetDev>& table, hipStream_t st);
+  fpt_status reset_run(const SliceArgs& a, uint64_t n_lanes, int R, bool refill,
+                       hipStream_t st);
+  fpt_status resolve_tuning(char* ws, hipStream_t st);
+  fpt_status simulate(void* workspace, int64_t* const* out_steps, uint64_t* out_hist,
+                      hipStream_t st);
+  fpt_status histogram(int32_t set, uint64_t* host_counts, fpt_moments* host_m);
+  fpt_status run_stats(fpt_run_stats* out);
+};
+
+void fill_moments(const MomDev& m, double dt, fpt_moments* out);
+fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision,
+                     const fpt_tuning* tuning, Plan** out);
+const char* last_error();
+
+}  // namespace fpt

@@ -1,0 +1,589 @@
+// runtime.cpp -- plans: validation and per-set constants, workspace layout,
+// the launch loop of fpt_simulate, histogram / moment readout, diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "autotune.hpp"
+#include "common.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace fpt {
+
+namespace {
+thread_local std::string g_error;
+}
+
+fpt_status fail(fpt_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return st;
+}
+
+void clear_error() { g_error.clear(); }
+
+const char* last_error() { return g_error.c_str(); }
+
+static bool finite_or_nan(double x) { return std::isfinite(x) || std::isnan(x); }
+
+fpt_status validate_params(const fpt_params& p, int i) {
+  if (p.model != FPT_UNDERDAMPED && p.model != FPT_OVERDAMPED)
+    return fail(FPT_E_INVAL, "set %d: model %d is not 0 (underdamped) or 1 (overdamped)", i,
+                p.model);
+  if (p.n_bins < 1 || p.n_bins > FPT_MAX_BINS)
+    return fail(FPT_E_INVAL, "set %d: n_bins %d outside [1, %d]", i, p.n_bins, FPT_MAX_BINS);
+  if (!(p.dt > 0.0) || !std::isfinite(p.dt))
+    return fail(FPT_E_INVAL, "set %d: dt must be finite and > 0", i);
+  if (!(p.T >= 0.0) || !std::isfinite(p.T))
+    return fail(FPT_E_INVAL, "set %d: T must be finite and >= 0", i);
+  if (!std::isfinite(p.alpha) || (p.model == FPT_UNDERDAMPED && p.alpha < 0.0))
+    return fail(FPT_E_INVAL, "set %d: alpha must be finite and >= 0", i);
+  if (!std::isfinite(p.V0) || !std::isfinite(p.gamma0) || !std::isfinite(p.ramp))
+    return fail(FPT_E_INVAL, "set %d: V0, gamma0 and ramp must be finite", i);
+  if (!finite_or_nan(p.phi0) || !finite_or_nan(p.v0) || !finite_or_nan(p.threshold))
+    return fail(FPT_E_INVAL, "set %d: phi0, v0, threshold must be finite or NaN", i);
+  if (std::isnan(p.phi0) && !(p.gamma0 >= -1.0 && p.gamma0 <= 1.0))
+    return fail(FPT_E_INVAL, "set %d: default phi0 = arcsin(gamma0) needs |gamma0| <= 1", i);
+  if (p.max_steps < 1 || p.max_steps > (int64_t(1) << 50))
+    return fail(FPT_E_INVAL, "set %d: max_steps %lld outside [1, 2^50]", i,
+                (long long)p.max_steps);
+  if (p.n_replicas < 0 || p.n_replicas > (int64_t(1) << 48))
+    return fail(FPT_E_INVAL, "set %d: n_replicas %lld outside [0, 2^48]", i,
+                (long long)p.n_replicas);
+  if (p.hist_k_max < 0 || p.hist_k_max > (int64_t(1) << 50))
+    return fail(FPT_E_INVAL, "set %d: hist_k_max outside [0, 2^50]", i);
+  return FPT_OK;
+}
+
+static float round_toward_minus_inf(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = std::nextafter(f, -INFINITY);
+  return f;
+}
+
+SetDev derive_set(const fpt_params& p) {
+  SetDev s;
+  std::memset(&s, 0, sizeof(s));
+  s.gamma0 = p.gamma0;
+  s.dgamma = p.ramp * p.dt;  // delta-gamma of Algorithm 3
+  s.dt = p.dt;
+  s.alpha = p.alpha;
+  s.V0 = p.V0;
+  if (p.model == FPT_UNDERDAMPED) {
+    const double D = p.alpha * p.T;  // D = beta theta, Eq. (9)
+    s.sigma = std::sqrt(2.0 * D * p.dt);
+  } else {
+    s.sigma = std::sqrt(2.0 * p.T * p.dt);
+  }
+  s.phi0 = std::isnan(p.phi0) ? std::asin(p.gamma0) : p.phi0;
+  s.v0 = std::isnan(p.v0) ? 0.0 : p.v0;
+  // default threshold: top of the washboard barrier, pi - arcsin(gamma)
+  s.th = std::isnan(p.threshold) ? 3.14159265358979323846 - s.phi0 : p.threshold;
+  s.h_f = (float)p.dt;
+  s.damp_f = (float)(1.0 - p.dt * p.alpha);
+  s.hV0_f = (float)(p.dt * p.V0);
+  s.sigma_f = (float)s.sigma;
+  s.V0_f = (float)p.V0;
+  // below th_near_f the compensated phase cannot exceed th: 8 float ulps of
+  // margin cover the compensation term and the rounding of th itself
+  float tn = round_toward_minus_inf(s.th);
+  for (int i = 0; i < 8; ++i) tn = std::nextafter(tn, -INFINITY);
+  s.th_near_f = tn;
+  s.phi0_f = (float)s.phi0;
+  s.c0_f = (float)((double)s.phi0_f - s.phi0);
+  s.v0_f = (float)s.v0;
+  s.max_steps = p.max_steps;
+  s.jmax = (uint64_t)(p.max_steps - 1) / 4;
+  s.k_hist = p.hist_k_max > 0 ? p.hist_k_max : p.max_steps;
+  s.seed = p.seed;
+  s.n_replicas = (uint64_t)p.n_replicas;
+  s.out_steps = nullptr;
+  s.hist_off = 0;
+  s.n_bins = (uint32_t)p.n_bins;
+  s.model = (uint32_t)p.model;
+  return s;
+}
+
+DeviceInfo device_info() {
+  DeviceInfo d;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+    (void)hipGetLastError();
+    return d;
+  }
+  if (hipGetDevice(&d.device) != hipSuccess) return d;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d.device) ==
+          hipSuccess &&
+      cus > 0)
+    d.cus = cus;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, d.device) == hipSuccess) {
+    std::string a = prop.gcnArchName;
+    d.arch = a.substr(0, a.find(':'));
+  }
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Plans
+
+static uint64_t align256(uint64_t x) { return round_up(x, 256); }
+
+fpt_status Plan::layout() {
+  const DeviceInfo di = device_info();
+  cus = di.cus;
+  arch = di.arch;
+  uint64_t slots;
+  if (tuning_req.schedule == FPT_SCHED_ONE_PER_LANE) {
+    slots = round_up(std::max<uint64_t>(total_flat, 1), kBlockThreads * kMaxReplicasPerLane);
+  } else {
+    slots = (uint64_t)cus * 4 * kMaxWavesPerSimd * kWave * kMaxReplicasPerLane;
+  }
+  max_slots = slots;
+  uint64_t off = 0;
+  off_sets = off;
+  off = align256(off + sizeof(SetDev) * sets.size());
+  off_chunks = off;
+  off = align256(off + sizeof(Chunk) * chunks.size());
+  off_ctr = off;
+  off = align256(off + sizeof(Counters));
+  off_mom = off;
+  off = align256(off + sizeof(MomDev) * sets.size());
+  off_hist = off;
+  off = align256(off + sizeof(uint64_t) * std::max<uint64_t>(hist_bins, 1));
+  off_st_phi = off;
+  off = align256(off + 8 * slots);
+  off_st_v = off;
+  off = align256(off + 8 * slots);
+  off_st_j = off;
+  off = align256(off + 8 * slots);
+  off_st_idx = off;
+  off = align256(off + 8 * slots);
+  off_st_set = off;
+  off = align256(off + 4 * slots);
+  ws_bytes = off;
+  return FPT_OK;
+}
+
+SliceArgs Plan::slice_args(char* ws, uint64_t* hist_dev, uint64_t n_lanes_) const {
+  SliceArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.sets = reinterpret_cast<const SetDev*>(ws + off_sets);
+  a.chunks = multi ? reinterpret_cast<const Chunk*>(ws + off_chunks) : nullptr;
+  a.chunk_mask = ~0ull;
+  a.ctr = reinterpret_cast<Counters*>(ws + off_ctr);
+  a.total = total_flat;
+  a.st_phi = reinterpret_cast<unsigned long long*>(ws + off_st_phi);
+  a.st_v = reinterpret_cast<unsigned long long*>(ws + off_st_v);
+  a.st_j = reinterpret_cast<unsigned long long*>(ws + off_st_j);
+  a.st_idx = reinterpret_cast<unsigned long long*>(ws + off_st_idx);
+  a.st_set = reinterpret_cast<uint32_t*>(ws + off_st_set);
+  a.n_lanes = n_lanes_;
+  a.hist = reinterpret_cast<unsigned long long*>(hist_dev);
+  a.mom = reinterpret_cast<MomDev*>(ws + off_mom);
+  a.blocks = 0;
+  a.refill = 0;
+  a.clamp = 0;
+  return a;
+}
+
+uint64_t Plan::lanes_for(const fpt_tuning& t) const {
+  const uint64_t R = (uint64_t)t.replicas_per_lane;
+  if (t.schedule == FPT_SCHED_ONE_PER_LANE)
+    return round_up((std::max<uint64_t>(total_flat, 1) + R - 1) / R, kBlockThreads);
+  uint64_t lanes = (uint64_t)cus * 4 * (uint64_t)t.waves_per_simd * kWave;
+  const uint64_t need = round_up((total_flat + R - 1) / R, kBlockThreads);
+  return std::max<uint64_t>(std::min(lanes, need), kBlockThreads);
+}
+
+Plan::~Plan() {
+  if (h_ctr) (void)hipHostFree(h_ctr);
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+}
+
+fpt_status Plan::ensure_host_resources(size_t n_events) {
+  if (!h_ctr) FPT_HIP(hipHostMalloc((void**)&h_ctr, sizeof(Counters), hipHostMallocDefault));
+  while (events.size() < n_events) {
+    hipEvent_t e;
+    FPT_HIP(hipEventCreate(&e));
+    events.push_back(e);
+  }
+  return FPT_OK;
+}
+
+// Reset counters, results and lane state, then bind every slot's first
+// replica.  `sets_dev` already holds the set table.
+fpt_status Plan::reset_run(const SliceArgs& a, uint64_t n_lanes_, int R, bool refill,
+                           hipStream_t st) {
+  FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(a.ctr),
+                          sizeof(Counters) / 8, 0ull, st));
+  FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(a.mom),
+                          sizeof(MomDev) / 8 * sets.size(), 0ull, st));
+  FPT_HIP(launch_fill_u64(a.hist, hist_bins, 0ull, st));
+  const uint64_t n_slots = n_lanes_ * (uint64_t)R;
+  const uint64_t n_assign = std::min<uint64_t>(n_slots, total_flat);
+  FPT_HIP(launch_init(precision == FPT_FP64, a, n_slots, n_assign, st));
+  if (refill) FPT_HIP(launch_fill_u64(&a.ctr->cursor, 1, n_assign, st));
+  return FPT_OK;
+}
+
+fpt_status Plan::upload_sets(char* ws, const std::vector<SetDev>& table,
+                             hipStream_t st) {
+  FPT_HIP(hipMemcpyAsync(ws + off_sets, table.data(), sizeof(SetDev) * table.size(),
+                         hipMemcpyHostToDevice, st));
+  if (multi && !chunks.empty())
+    FPT_HIP(hipMemcpyAsync(ws + off_chunks, chunks.data(), sizeof(Chunk) * chunks.size(),
+                           hipMemcpyHostToDevice, st));
+  return FPT_OK;
+}
+
+// Upper bound on launches: no replica needs more than jmax+1 blocks, and all
+// replicas together cannot need more than their summed blocks spread over the
+// slots, plus the longest single replica for the tail.
+uint64_t Plan::launch_bound(uint64_t n_slots, int blocks) const {
+  uint64_t longest = 0;
+  long double work = 0;
+  for (const SetDev& s : sets) {
+    longest = std::max<uint64_t>(longest, s.jmax + 1);
+    work += (long double)s.n_replicas * (long double)(s.jmax + 1);
+  }
+  const long double per_launch = (long double)n_slots * (long double)blocks;
+  const uint64_t spread = (uint64_t)(work / per_launch) + 1;
+  return 2 * (spread + longest / (uint64_t)blocks + 1) + 16;
+}
+
+fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
+                          uint64_t* out_hist, hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  char* ws = static_cast<char*>(workspace);
+  if (!ws) return fail(FPT_E_INVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(FPT_E_INVAL, "workspace must be 256-byte aligned");
+  hist_dev = out_hist ? out_hist : reinterpret_cast<uint64_t*>(ws + off_hist);
+  ws_mom_ptr = reinterpret_cast<MomDev*>(ws + off_mom);
+  ran = false;
+  stream = st;
+
+  FPT_TRY(resolve_tuning(ws, st));
+  const int R = tuning.replicas_per_lane;
+  const bool refill = tuning.schedule == FPT_SCHED_REFILL;
+  n_lanes = lanes_for(tuning);
+  const uint64_t n_slots = n_lanes * (uint64_t)R;
+  if (n_slots > max_slots)
+    return fail(FPT_E_INVAL, "launch shape needs %llu slots, workspace holds %llu",
+                (unsigned long long)n_slots, (unsigned long long)max_slots);
+  const int blocks = tuning.steps_per_launch / 4;
+
+  std::vector<SetDev> table = sets;
+  for (size_t i = 0; i < table.size(); ++i)
+    table[i].out_steps = out_steps ? out_steps[i] : nullptr;
+  FPT_TRY(upload_sets(ws, table, st));
+
+  SliceArgs a = slice_args(ws, hist_dev, n_lanes);
+  a.blocks = blocks;
+  a.refill = refill ? 1 : 0;
+  FPT_TRY(reset_run(a, n_lanes, R, refill, st));
+
+  const uint32_t groups = (uint32_t)(n_lanes / kBlockThreads);
+  const bool fp64 = precision == FPT_FP64;
+  const uint64_t bound = launch_bound(n_slots, blocks);
+  stats = fpt_run_stats{};
+  stats.tuning = tuning;
+  int group = 1;
+  int64_t launches = 0;
+  double kernel_ms = 0.0;
+  bool finished = total_replicas == 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+  size_t ev_used = 0;
+
+  if (tuning.use_graph && !finished) {
+    // capture a fixed group of launches plus the status copy once, replay it
+    group = 8;
+    FPT_TRY(ensure_host_resources(2 + 1));
+    if (graph_exec) {
+      (void)hipGraphExecDestroy(graph_exec);
+      graph_exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    FPT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t cap_err = hipSuccess;
+    for (int i = 0; i < group && cap_err == hipSuccess; ++i)
+      cap_err = launch_slice(fp64, model, R, multi, a, groups, st);
+    if (cap_err == hipSuccess)
+      cap_err = hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st);
+    hipError_t end_err = hipStreamEndCapture(st, &g);
+    if (cap_err != hipSuccess || end_err != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(FPT_E_DEVICE, "graph capture failed: %s",
+                  hipGetErrorString(cap_err != hipSuccess ? cap_err : end_err));
+    }
+    hipError_t inst = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (inst != hipSuccess)
+      return fail(FPT_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(inst));
+    while (!finished) {
+      FPT_HIP(hipEventRecord(events[0], st));
+      FPT_HIP(hipGraphLaunch(graph_exec, st));
+      FPT_HIP(hipEventRecord(events[1], st));
+      FPT_HIP(hipEventSynchronize(events[1]));
+      float ms = 0.f;
+      FPT_HIP(hipEventElapsedTime(&ms, events[0], events[1]));
+      kernel_ms += ms;
+      launches += group;
+      finished = h_ctr->done >= total_replicas;
+      if (!finished && (uint64_t)launches > bound)
+        return fail(FPT_E_DEVICE, "run did not finish within %llu launches",
+                    (unsigned long long)bound);
+    }
+  } else {
+    while (!finished) {
+      FPT_TRY(ensure_host_resources(ev_used + 2 * group + 1));
+      for (int i = 0; i < group; ++i) {
+        hipEvent_t e0 = events[ev_used++], e1 = events[ev_used++];
+        FPT_HIP(hipEventRecord(e0, st));
+        FPT_HIP(launch_slice(fp64, model, R, multi, a, groups, st));
+        FPT_HIP(hipEventRecord(e1, st));
+        marks.emplace_back(e0, e1);
+        ++launches;
+      }
+      FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+      hipEvent_t sync = events[ev_used++];
+      FPT_HIP(hipEventRecord(sync, st));
+      FPT_HIP(hipEventSynchronize(sync));
+      for (auto& m : marks) {
+        float ms = 0.f;
+        FPT_HIP(hipEventElapsedTime(&ms, m.first, m.second));
+        kernel_ms += ms;
+      }
+      marks.clear();
+      ev_used = 0;
+      finished = h_ctr->done >= total_replicas;
+      if (!finished && (uint64_t)launches > bound)
+        return fail(FPT_E_DEVICE, "run did not finish within %llu launches",
+                    (unsigned long long)bound);
+      group = std::min(group * 2, 8);
+    }
+  }
+  if (total_replicas == 0) FPT_TRY(ensure_host_resources(1));
+  if (total_replicas > 0) stats.lane_steps = h_ctr->lane_steps;
+  stats.n_launches = launches;
+  stats.kernel_ms = kernel_ms;
+  stats.wall_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+          .count();
+  ran = true;
+  return FPT_OK;
+}
+
+fpt_status Plan::histogram(int32_t set, uint64_t* host_counts, fpt_moments* host_m) {
+  if (!ran) return fail(FPT_E_STATE, "fpt_histogram before a finished fpt_simulate");
+  if (set < 0 || set >= (int32_t)sets.size())
+    return fail(FPT_E_INVAL, "set %d outside [0, %zu)", set, sets.size());
+  FPT_HIP(hipStreamSynchronize(stream));
+  const SetDev& s = sets[(size_t)set];
+  if (host_counts)
+    FPT_HIP(hipMemcpy(host_counts, hist_dev + s.hist_off, sizeof(uint64_t) * s.n_bins,
+                      hipMemcpyDeviceToHost));
+  if (host_m) {
+    MomDev m;
+    FPT_HIP(hipMemcpy(&m, ws_mom_ptr + set, sizeof(MomDev), hipMemcpyDeviceToHost));
+    fill_moments(m, s.dt, host_m);
+  }
+  return FPT_OK;
+}
+
+void fill_moments(const MomDev& m, double dt, fpt_moments* out) {
+  out->n_escaped = m.n_esc;
+  out->n_censored = m.n_cens;
+  out->n_overflow = m.n_over;
+  out->sum_k = m.sum_k;
+  out->sum_k2_lo = m.sum_k2_lo;
+  out->sum_k2_hi = m.sum_k2_hi;
+  out->mean_t = NAN;
+  out->se_t = NAN;
+  const uint64_t n = m.n_esc;
+  if (n > 0) out->mean_t = dt * ((double)m.sum_k / (double)n);
+  if (n > 1) {
+    const unsigned __int128 k2 = ((unsigned __int128)m.sum_k2_hi << 64) | m.sum_k2_lo;
+    const unsigned __int128 m2 =
+        (unsigned __int128)n * k2 - (unsigned __int128)m.sum_k * (unsigned __int128)m.sum_k;
+    out->se_t = dt * std::sqrt((double)m2 / ((double)n * (double)n * (double)(n - 1)));
+  }
+}
+
+fpt_status Plan::run_stats(fpt_run_stats* out) {
+  if (!ran) return fail(FPT_E_STATE, "fpt_plan_stats before a finished fpt_simulate");
+  FPT_HIP(hipStreamSynchronize(stream));
+  uint64_t rs = 0;
+  std::vector<MomDev> m(sets.size());
+  if (!sets.empty())
+    FPT_HIP(hipMemcpy(m.data(), ws_mom_ptr, sizeof(MomDev) * sets.size(),
+                      hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < sets.size(); ++i)
+    rs += m[i].sum_k + m[i].n_cens * (uint64_t)sets[i].max_steps;
+  *out = stats;
+  out->replica_steps = rs;
+  return FPT_OK;
+}
+
+fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision,
+                     const fpt_tuning* tuning, Plan** out) {
+  if (!params || n_sets < 1) return fail(FPT_E_INVAL, "need at least one parameter set");
+  if (n_sets > (1 << 20)) return fail(FPT_E_INVAL, "at most 2^20 parameter sets");
+  if (precision != FPT_FP64 && precision != FPT_FP32C)
+    return fail(FPT_E_INVAL, "precision %d is not FPT_FP64 or FPT_FP32C", precision);
+  for (int32_t i = 0; i < n_sets; ++i) FPT_TRY(validate_params(params[i], i));
+  for (int32_t i = 1; i < n_sets; ++i)
+    if (params[i].model != params[0].model)
+      return fail(FPT_E_INVAL, "set %d: all sets of a plan must share one model", i);
+  fpt_tuning t{};
+  if (tuning) t = *tuning;
+  if (t.schedule != FPT_SCHED_REFILL && t.schedule != FPT_SCHED_ONE_PER_LANE)
+    return fail(FPT_E_INVAL, "tuning.schedule %d unknown", t.schedule);
+  if (t.replicas_per_lane < 0 || t.replicas_per_lane > kMaxReplicasPerLane)
+    return fail(FPT_E_INVAL, "tuning.replicas_per_lane must be 0, 1 or 2");
+  if (t.waves_per_simd < 0 || t.waves_per_simd > kMaxWavesPerSimd)
+    return fail(FPT_E_INVAL, "tuning.waves_per_simd must be in [0, %d]", kMaxWavesPerSimd);
+  if (t.steps_per_launch < 0 || t.steps_per_launch % 4 || t.steps_per_launch > (1 << 26))
+    return fail(FPT_E_INVAL, "tuning.steps_per_launch must be a multiple of 4 in [0, 2^26]");
+
+  Plan* p = new Plan();
+  p->precision = precision;
+  p->model = params[0].model;
+  p->tuning_req = t;
+  p->multi = n_sets > 1;
+  uint64_t off = 0;
+  for (int32_t i = 0; i < n_sets; ++i) {
+    p->params.push_back(params[i]);
+    SetDev s = derive_set(params[i]);
+    s.hist_off = off;
+    off += s.n_bins;
+    p->total_replicas += s.n_replicas;
+    p->sets.push_back(s);
+  }
+  p->hist_bins = off;
+  if (p->multi) {
+    for (int32_t i = 0; i < n_sets; ++i) {
+      const uint64_t n = (uint64_t)params[i].n_replicas;
+      for (uint64_t first = 0; first < n; first += kChunk) {
+        Chunk c;
+        c.set = (uint32_t)i;
+        c.count = (uint32_t)std::min<uint64_t>(kChunk, n - first);
+        c.first = first;
+        p->chunks.push_back(c);
+      }
+    }
+    p->total_flat = (uint64_t)p->chunks.size() * kChunk;
+  } else {
+    p->total_flat = p->total_replicas;
+  }
+  p->layout();
+  *out = p;
+  return FPT_OK;
+}
+
+}  // namespace fpt
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+using fpt::Plan;
+
+struct fpt_plan_s {
+  Plan* impl;
+};
+
+extern "C" {
+
+const char* fpt_last_error(void) { return fpt::last_error(); }
+
+int32_t fpt_api_version(void) { return FPT_API_VERSION; }
+
+fpt_status fpt_plan(const fpt_params* sets, int32_t n_sets, int32_t precision,
+                    const fpt_tuning* tuning, fpt_plan_t* out) {
+  if (!out) return fpt::fail(FPT_E_INVAL, "out is NULL");
+  *out = nullptr;
+  Plan* p = nullptr;
+  fpt_status st = fpt::make_plan(sets, n_sets, precision, tuning, &p);
+  if (st != FPT_OK) return st;
+  *out = new fpt_plan_s{p};
+  return FPT_OK;
+}
+
+fpt_status fpt_plan_workspace(fpt_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fpt::fail(FPT_E_INVAL, "NULL argument");
+  *bytes = plan->impl->ws_bytes;
+  return FPT_OK;
+}
+
+fpt_status fpt_simulate(fpt_plan_t plan, void* workspace, int64_t* const* out_steps,
+                        uint64_t* out_hist, void* stream) {
+  if (!plan) return fpt::fail(FPT_E_INVAL, "plan is NULL");
+  return plan->impl->simulate(workspace, out_steps, out_hist,
+                              static_cast<hipStream_t>(stream));
+}
+
+fpt_status fpt_histogram(fpt_plan_t plan, int32_t set, uint64_t* host_counts,
+                         fpt_moments* host_m) {
+  if (!plan) return fpt::fail(FPT_E_INVAL, "plan is NULL");
+  return plan->impl->histogram(set, host_counts, host_m);
+}
+
+fpt_status fpt_plan_stats(fpt_plan_t plan, fpt_run_stats* out) {
+  if (!plan || !out) return fpt::fail(FPT_E_INVAL, "NULL argument");
+  return plan->impl->run_stats(out);
+}
+
+void fpt_plan_destroy(fpt_plan_t plan) {
+  if (!plan) return;
+  delete plan->impl;
+  delete plan;
+}
+
+fpt_status fpt_rng_words(uint64_t seed, uint64_t replica0, int64_t n_rep, uint64_t block0,
+                         int64_t n_blk, uint32_t* out, void* stream) {
+  if (n_rep < 0 || n_blk < 0 || (n_rep * n_blk > 0 && !out))
+    return fpt::fail(FPT_E_INVAL, "bad sizes or NULL output");
+  FPT_HIP(fpt::launch_rng_words(seed, replica0, (uint64_t)n_rep, block0, (uint64_t)n_blk, out,
+                                static_cast<hipStream_t>(stream)));
+  return FPT_OK;
+}
+
+fpt_status fpt_normals(uint64_t seed, uint64_t replica0, int64_t n_rep, uint64_t block0,
+                       int64_t n_blk, int32_t precision, void* out, void* stream) {
+  if (n_rep < 0 || n_blk < 0 || (n_rep * n_blk > 0 && !out))
+    return fpt::fail(FPT_E_INVAL, "bad sizes or NULL output");
+  if (precision != FPT_FP64 && precision != FPT_FP32C)
+    return fpt::fail(FPT_E_INVAL, "precision %d unknown", precision);
+  FPT_HIP(fpt::launch_normals(precision == FPT_FP64, seed, replica0, (uint64_t)n_rep, block0,
+                              (uint64_t)n_blk, out, static_cast<hipStream_t>(stream)));
+  return FPT_OK;
+}
+
+fpt_status fpt_trajectory(const fpt_params* params, uint64_t replica, int64_t n_steps,
+                          int32_t precision, double* out_phi, double* out_v, void* stream) {
+  if (!params || n_steps < 0 || (n_steps > 0 && (!out_phi || !out_v)))
+    return fpt::fail(FPT_E_INVAL, "bad arguments");
+  if (precision != FPT_FP64 && precision != FPT_FP32C)
+    return fpt::fail(FPT_E_INVAL, "precision %d unknown", precision);
+  FPT_TRY(fpt::validate_params(*params, 0));
+  const fpt::SetDev sd = fpt::derive_set(*params);
+  FPT_HIP(fpt::launch_trajectory(precision == FPT_FP64, params->model, sd, replica, n_steps,
+                                 out_phi, out_v, static_cast<hipStream_t>(stream)));
+  return FPT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/fpt.h declares, and its host-side validation rejects bad input with
+the documented status codes."""
+
+import math
+import os
+import re
+
+import pytest
+
+from paper_1802_05065_amd import _lib, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1802_05065_amd import build
+
+        build.build()
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fpt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+    bound = {s[0] for s in _lib.SIGNATURES}
+    assert set(names) == bound
+
+
+def test_version(lib):
+    assert _lib.fpt_api_version() == 1
+
+
+def test_plan_accepts_workloads_without_gpu(lib):
+    for sets in ([workloads.plain_escape()], [workloads.switching_ramp()],
+                 [workloads.uneven_overdamped()], workloads.batched_sets(16)):
+        for prec in ("fp64", "fp32c"):
+            h = _lib.fpt_plan(sets, prec)
+            try:
+                assert _lib.fpt_plan_workspace(h) > 0
+            finally:
+                _lib.fpt_plan_destroy(h)
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("n_bins", 0, "n_bins"),
+    ("n_bins", 4097, "n_bins"),
+    ("dt", 0.0, "dt"),
+    ("dt", math.inf, "dt"),
+    ("T", -1.0, "T must"),
+    ("max_steps", 0, "max_steps"),
+    ("n_replicas", -5, "n_replicas"),
+    ("model", 7, "model"),
+    ("alpha", -0.1, "alpha"),
+    ("threshold", math.inf, "threshold"),
+])
+def test_plan_rejects_bad_params(lib, field, value, needle):
+    p = workloads.plain_escape()
+    p[field] = value
+    with pytest.raises(_lib.FptError) as e:
+        _lib.fpt_plan([p], "fp64")
+    assert e.value.status == _lib.FPT_E_INVAL
+    assert needle in e.value.message
+
+
+def test_default_phi0_needs_bias_in_range(lib):
+    p = workloads.plain_escape()
+    p["phi0"] = math.nan
+    p["gamma0"] = 1.5
+    with pytest.raises(_lib.FptError) as e:
+        _lib.fpt_plan([p], "fp64")
+    assert "arcsin" in e.value.message
+
+
+def test_plan_rejects_mixed_models_and_bad_tuning(lib):
+    a = workloads.plain_escape()
+    b = workloads.uneven_overdamped(n_replicas=10)
+    with pytest.raises(_lib.FptError):
+        _lib.fpt_plan([a, b], "fp64")
+    for t in (dict(steps_per_launch=6), dict(replicas_per_lane=3), dict(waves_per_simd=9),
+              dict(schedule=5)):
+        with pytest.raises(_lib.FptError):
+            _lib.fpt_plan([a], "fp64", t)
+    with pytest.raises(_lib.FptError):
+        _lib.fpt_plan([a], 7)
+
+
+def test_histogram_before_simulate_is_a_state_error(lib):
+    h = _lib.fpt_plan([workloads.plain_escape()], "fp64")
+    try:
+        with pytest.raises(_lib.FptError) as e:
+            _lib.fpt_histogram(h, 0, 64)
+        assert e.value.status == _lib.FPT_E_STATE
+    finally:
+        _lib.fpt_plan_destroy(h)
+
+
+def test_null_arguments(lib):
+    import ctypes
+
+    assert lib.fpt_plan(None, 1, 0, None, ctypes.byref(ctypes.c_void_p())) == _lib.FPT_E_INVAL
+    assert lib.fpt_plan_workspace(None, None) == _lib.FPT_E_INVAL
+    assert lib.fpt_simulate(None, None, None, None, None) == _lib.FPT_E_INVAL
+    assert lib.fpt_server_create(None, 0, 0, 0, None, None,
+                                 ctypes.byref(ctypes.c_void_p())) == _lib.FPT_E_INVAL
+    assert lib.fpt_submit(None, None, None) == _lib.FPT_E_INVAL
+    assert lib.fpt_poll(None, 1, None, None, None) == _lib.FPT_E_INVAL
+    assert "NULL" in _lib.last_error()
+    lib.fpt_plan_destroy(None)
+    lib.fpt_server_destroy(None)
+
+
+def test_workspace_grows_with_one_per_lane_schedule(lib):
+    p = workloads.uneven_overdamped(n_replicas=2 ** 22)
+    h1 = _lib.fpt_plan([p], "fp32c", dict(schedule=0))
+    h2 = _lib.fpt_plan([p], "fp32c", dict(schedule=1))
+    try:
+        # one lane per replica: state for all 2^22 replicas
+        assert _lib.fpt_plan_workspace(h2) >= 36 * 2 ** 22
+        assert _lib.fpt_plan_workspace(h1) < _lib.fpt_plan_workspace(h2)
+    finally:
+        _lib.fpt_plan_destroy(h1)
+        _lib.fpt_plan_destroy(h2)

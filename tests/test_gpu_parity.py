@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Bars: Philox words bit-exact; FP64 escape steps identical for >= 99% of
+replicas; histograms and integer moments exact given the steps; FP32C runs
+statistically equal to FP64 (two-sample KS p > 0.01 with independent seeds,
+mean within 3 combined standard errors); results independent of the launch
+shape, of batching and of serving."""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from paper_1802_05065_amd import api, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(p):
+    return oracle.OracleParams(**workloads.to_oracle_kwargs(p))
+
+
+def _steps(res, i=0):
+    return res.steps[i].cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# generator and normals
+
+
+def test_rng_words_bit_exact():
+    words = api.rng_words(seed=0xC0FFEE1234, replica0=0, n_rep=64, block0=0, n_blk=16)
+    for r in range(0, 64, 7):
+        for b in range(16):
+            assert words[r, b].tolist() == oracle.rng_words(0xC0FFEE1234, r, b).tolist()
+    far = api.rng_words(seed=2**64 - 3, replica0=2**33 + 5, n_rep=3, block0=2**40, n_blk=5)
+    for r in range(3):
+        for b in range(5):
+            ref = oracle.rng_words(2**64 - 3, 2**33 + 5 + r, 2**40 + b)
+            assert far[r, b].tolist() == ref.tolist()
+
+
+def test_normals_fp64_match_oracle():
+    z = api.normals(seed=7, replica0=0, n_rep=32, block0=0, n_blk=64, precision="fp64")
+    ref = np.array([[oracle.normals(7, r, b) for b in range(64)] for r in range(32)])
+    np.testing.assert_allclose(z, ref, rtol=4e-15, atol=4e-15)
+
+
+def test_normals_fp32_match_oracle_and_are_gaussian():
+    z = api.normals(seed=7, replica0=0, n_rep=32, block0=0, n_blk=64, precision="fp32c")
+    ref = np.array([[oracle.normals(7, r, b) for b in range(64)] for r in range(32)])
+    np.testing.assert_allclose(z.astype(np.float64), ref, rtol=1e-5, atol=2e-5)
+    big = api.normals(seed=9, replica0=0, n_rep=4096, block0=0, n_blk=256,
+                      precision="fp32c").astype(np.float64).ravel()
+    n = big.size
+    assert abs(big.mean()) < 4 / math.sqrt(n)
+    assert abs(big.var() - 1) < 4 * math.sqrt(2 / n)
+    assert stats.kstest(big[:2_000_000], "norm").pvalue > 1e-3
+    assert np.abs(big).max() <= math.sqrt(66 * math.log(2)) + 1e-4
+
+
+# ---------------------------------------------------------------------------
+# the step: trajectories
+
+
+@pytest.mark.parametrize("maker", [workloads.plain_escape, workloads.uneven_overdamped])
+def test_trajectory_fp64_matches_oracle(maker):
+    p = maker(n_replicas=4)
+    p = dict(p, threshold=1e300)
+    phi, v = api.trajectory(p, replica=3, n_steps=5003, precision="fp64")
+    rphi, rv = oracle.trajectory(_op(p), 3, 5003)
+    np.testing.assert_allclose(phi, rphi, rtol=0, atol=1e-9)
+    if p["model"] == 0:
+        np.testing.assert_allclose(v, rv, rtol=0, atol=1e-9)
+    # early steps agree to the last bits
+    np.testing.assert_allclose(phi[:50], rphi[:50], rtol=1e-15, atol=0)
+
+
+def test_trajectory_fp32c_tracks_fp64():
+    p = dict(workloads.switching_ramp(n_replicas=1), ramp=1e-3, threshold=1e300)
+    phi32, v32 = api.trajectory(p, replica=0, n_steps=4000, precision="fp32c")
+    phi64, v64 = api.trajectory(p, replica=0, n_steps=4000, precision="fp64")
+    assert np.abs(phi32 - phi64).max() < 2e-4
+    assert np.abs(v32 - v64).max() < 2e-4
+
+
+# ---------------------------------------------------------------------------
+# escape steps, histograms, moments
+
+
+FIXED = dict(replicas_per_lane=1, waves_per_simd=4, steps_per_launch=4096)
+
+
+def test_plain_escape_fp64_full_matches_oracle():
+    p = workloads.plain_escape()
+    res = api.simulate(p, "fp64", FIXED)
+    gpu = _steps(res)
+    ref = oracle.escape_steps(_op(p), 0, p["n_replicas"])
+    same = np.mean(gpu == ref)
+    print(f"identical FP64 escape steps: {same:.5f}")
+    assert same >= 0.99
+    # histogram and moments are exact functions of the steps
+    h, m = oracle.histogram(gpu, p["n_bins"], p["hist_k_max"], p["dt"])
+    assert res.counts[0].tolist() == h.tolist()
+    for k in ("n_escaped", "n_censored", "n_overflow", "sum_k", "sum_k2"):
+        assert res.moments[0][k] == m[k], k
+    assert res.moments[0]["mean_t"] == pytest.approx(m["mean_t"], rel=1e-15)
+    assert res.moments[0]["se_t"] == pytest.approx(m["se_t"], rel=1e-12)
+    assert res.stats["replica_steps"] == oracle.replica_steps(gpu, p["max_steps"])
+
+
+def test_plain_escape_fp32c_statistics():
+    n = 2 ** 15
+    p32 = workloads.plain_escape(n_replicas=n, seed=101)
+    p64 = workloads.plain_escape(n_replicas=n, seed=202)
+    s32 = _steps(api.simulate(p32, "fp32c", FIXED))
+    s64 = _steps(api.simulate(p64, "fp64", FIXED))
+    assert (s32 > 0).all() and (s64 > 0).all()
+    ks = stats.ks_2samp(s32, s64)
+    se = math.sqrt(s32.var() / n + s64.var() / n)
+    print(f"KS p = {ks.pvalue:.3f}; mean fp32c {s32.mean():.1f} fp64 {s64.mean():.1f} "
+          f"(3 SE = {3 * se:.1f})")
+    assert ks.pvalue > 0.01
+    assert abs(s32.mean() - s64.mean()) < 3 * se
+    # same seed: a different sample path, error stated
+    same32 = _steps(api.simulate(p64, "fp32c", FIXED))
+    print(f"same-seed identical fraction {np.mean(same32 == s64):.3f}, "
+          f"mean |dk| {np.abs(same32 - s64).mean():.1f}")
+
+
+TUNINGS = [
+    dict(replicas_per_lane=1, waves_per_simd=8, steps_per_launch=1024),
+    dict(replicas_per_lane=2, waves_per_simd=2, steps_per_launch=4096),
+    dict(replicas_per_lane=1, waves_per_simd=1, steps_per_launch=256),
+    dict(schedule=1, replicas_per_lane=1, steps_per_launch=2048),
+    dict(schedule=1, replicas_per_lane=2, steps_per_launch=512),
+    dict(replicas_per_lane=1, waves_per_simd=4, steps_per_launch=1024, use_graph=1),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_results_independent_of_launch_shape(prec):
+    p = workloads.uneven_overdamped(n_replicas=6000, seed=3)
+    p["max_steps"] = 60_001  # some censoring, cap not a multiple of 4
+    base = api.simulate(p, prec, TUNINGS[0])
+    b_steps = _steps(base)
+    assert (b_steps == -1).any() and (b_steps > 0).any()
+    for t in TUNINGS[1:]:
+        r = api.simulate(p, prec, t)
+        assert np.array_equal(_steps(r), b_steps), t
+        assert r.counts[0].tolist() == base.counts[0].tolist(), t
+        assert r.moments[0] == base.moments[0], t
+
+
+def test_uneven_overdamped_fp64_sample_matches_oracle():
+    p = workloads.uneven_overdamped(n_replicas=2 ** 14, seed=3)
+    gpu = _steps(api.simulate(p, "fp64", FIXED))
+    idx = np.arange(0, 2 ** 14, 97)
+    ref = np.array([oracle.escape_steps(_op(p), int(i), 1)[0] for i in idx])
+    assert np.mean(gpu[idx] == ref) >= 0.99
+
+
+def test_edge_cases_match_oracle():
+    base = workloads.plain_escape(n_replicas=1000, seed=5)
+    cases = [
+        dict(base, n_replicas=0),
+        dict(base, n_replicas=1),
+        dict(base, n_replicas=1000),                       # ragged: not a multiple of 64
+        dict(base, max_steps=1),
+        dict(base, max_steps=7, hist_k_max=7, n_bins=3),  # cap inside a 4-step block
+        dict(base, threshold=-1.0),                        # escapes at the first step
+        dict(base, max_steps=999, hist_k_max=500),         # censored + overflow
+        dict(base, T=0.0),                                 # noise-free: all censored
+    ]
+    for c in cases:
+        res = api.simulate(c, "fp64", FIXED)
+        n = c["n_replicas"]
+        m = res.moments[0]
+        assert m["n_escaped"] + m["n_censored"] == n
+        if n == 0:
+            assert res.counts[0].sum() == 0
+            continue
+        gpu = _steps(res)
+        ref = oracle.escape_steps(_op(c), 0, n)
+        assert np.mean(gpu == ref) >= 0.99, c
+        h, mm = oracle.histogram(gpu, c["n_bins"], c["hist_k_max"] or c["max_steps"], c["dt"])
+        assert res.counts[0].tolist() == h.tolist()
+        assert m["n_overflow"] == mm["n_overflow"]
+        if c["threshold"] == -1.0:
+            assert (gpu == 1).all()
+        if c["T"] == 0.0:
+            assert (gpu == -1).all()
+
+
+def test_batched_sets_equal_each_set_alone():
+    sets = workloads.batched_sets(n_sets=6, seed=4, log2_min=6, log2_max=9, ramp_scale=300.0)
+    for prec in ("fp64", "fp32c"):
+        batch = api.simulate(sets, prec, dict(replicas_per_lane=1, waves_per_simd=2,
+                                              steps_per_launch=2048))
+        for i, s in enumerate(sets):
+            alone = api.simulate(s, prec, dict(replicas_per_lane=2, waves_per_simd=1,
+                                               steps_per_launch=1024))
+            assert np.array_equal(_steps(batch, i), _steps(alone)), (prec, i)
+            assert batch.counts[i].tolist() == alone.counts[0].tolist()
+            assert batch.moments[i] == alone.moments[0]
+    # FP64 batch against the oracle on sampled replicas
+    batch = api.simulate(sets, "fp64", None)
+    for i, s in enumerate(sets[:3]):
+        ref = oracle.escape_steps(_op(s), 0, 8)
+        assert np.mean(_steps(batch, i)[:8] == ref) >= 0.99
+
+
+def test_serving_alone_equals_mix():
+    import time
+
+    import torch
+
+    from paper_1802_05065_amd import _lib
+
+    jobs = workloads.batched_sets(n_sets=5, seed=9, log2_min=7, log2_max=10, ramp_scale=300.0)
+    pool = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    base = pool.data_ptr() + ((-pool.data_ptr()) % 256)
+    stream = torch.cuda.current_stream()
+    srv = _lib.fpt_server_create(base, (256 << 20) - 256, "fp32c", 0,
+                                 dict(waves_per_simd=2, steps_per_launch=1024),
+                                 stream.cuda_stream)
+    try:
+        ids = [_lib.fpt_submit(srv, j) for j in jobs]
+        results = {}
+        t0 = time.time()
+        while len(results) < len(ids) and time.time() - t0 < 90:
+            for i, jid in enumerate(ids):
+                if i not in results:
+                    r = _lib.fpt_poll(srv, jid, jobs[i]["n_bins"])
+                    if r is not None:
+                        results[i] = r
+            time.sleep(0.01)
+        assert len(results) == len(ids)
+        st = _lib.fpt_server_stats_get(srv)
+        assert st["finished"] == len(ids)
+    finally:
+        _lib.fpt_server_destroy(srv)
+    for i, j in enumerate(jobs):
+        alone = api.simulate(j, "fp32c", FIXED, record_steps=False)
+        counts, mom, lat = results[i]
+        assert counts.tolist() == alone.counts[0].tolist(), i
+        for k in ("n_escaped", "n_censored", "n_overflow", "sum_k", "sum_k2"):
+            assert mom[k] == alone.moments[0][k], (i, k)
+        assert lat > 0
