@@ -106,10 +106,12 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
 
-    # library load, tuning of both precisions on small plans (untimed)
-    for prec in ("fp32c", "fp64"):
-        api.simulate(workloads.switching_ramp(n_replicas=2 ** 12, seed=99) | dict(
-            ramp=1e-3, max_steps=20_100, hist_k_max=20_000), prec)
+    # library load and autotuning of both precisions (untimed): plans of the
+    # same size and shape with a 1000x faster ramp, so the tuner sees the
+    # real occupancy
+    for prec, n in (("fp32c", args.replicas), ("fp64", args.fp64_replicas)):
+        api.simulate(workloads.switching_ramp(n_replicas=n, seed=99) | dict(
+            ramp=1e-3, max_steps=20_100, hist_k_max=20_000), prec, record_steps=False)
 
     p32 = workloads.switching_ramp(n_replicas=args.replicas, seed=2)
     plan32 = api.Plan([p32], "fp32c", None, dev)

@@ -5,8 +5,9 @@
 // lane R (register-level ILP), resident waves per SIMD W (occupancy) and steps
 // per launch S.  Candidates run a few short launches on the plan's own
 // parameter sets (outputs discarded, counters reset afterwards); the shape
-// with the highest measured slot-steps/s wins.  S is then sized so that one
-// launch lasts about FPT_LAUNCH_MS milliseconds (default 40).  Winners are
+// with the highest measured slot-steps/s wins.  S is then sized from the
+// winner's steps/s per resident slot so that one launch lasts about
+// FPT_LAUNCH_MS milliseconds (default 40).  Winners are
 // cached in memory and in a JSON-lines file (FPT_TUNE_CACHE, default
 // $HOME/.cache/fpt_tune.jsonl), one object per key.
 #include <hip/hip_runtime.h>
@@ -47,8 +48,10 @@ void load_file_locked() {
     char key[256];
     TuneEntry e;
     if (std::sscanf(line,
-                    "{\"key\": \"%255[^\"]\", \"R\": %d, \"W\": %d, \"rate\": %lf}", key,
-                    &e.replicas_per_lane, &e.waves_per_simd, &e.slot_steps_per_s) == 4)
+                    "{\"key\": \"%255[^\"]\", \"R\": %d, \"W\": %d, \"rate\": %lf, "
+                    "\"slot_rate\": %lf}",
+                    key, &e.replicas_per_lane, &e.waves_per_simd, &e.slot_steps_per_s,
+                    &e.per_slot_steps_per_s) == 5)
       g_cache[key] = e;
   }
   std::fclose(f);
@@ -87,18 +90,21 @@ void tune_store(const std::string& key, const TuneEntry& e) {
   const std::string path = cache_path();
   FILE* f = std::fopen(path.c_str(), "a");
   if (!f) return;  // the cache file is an optimisation only
-  std::fprintf(f, "{\"key\": \"%s\", \"R\": %d, \"W\": %d, \"rate\": %.6e}\n", key.c_str(),
-               e.replicas_per_lane, e.waves_per_simd, e.slot_steps_per_s);
+  std::fprintf(f,
+               "{\"key\": \"%s\", \"R\": %d, \"W\": %d, \"rate\": %.6e, \"slot_rate\": %.6e}\n",
+               key.c_str(), e.replicas_per_lane, e.waves_per_simd, e.slot_steps_per_s,
+               e.per_slot_steps_per_s);
   std::fclose(f);
 }
 
 // Measure one candidate shape: three launches of 256 blocks (1024 steps),
 // the last two timed.  Returns slot-steps/s or a negative value on error.
 static fpt_status trial(Plan& p, char* ws, hipStream_t st, const fpt_tuning& t,
-                        double* rate) {
+                        double* rate, double* slot_rate) {
   const int R = t.replicas_per_lane;
   const bool refill = t.schedule == FPT_SCHED_REFILL;
   const uint64_t lanes = p.lanes_for(t);
+  *slot_rate = 0.0;
   if (lanes * (uint64_t)R > p.max_slots) {
     *rate = -1.0;
     return FPT_OK;
@@ -128,6 +134,7 @@ static fpt_status trial(Plan& p, char* ws, hipStream_t st, const fpt_tuning& t,
   FPT_HIP(hipEventElapsedTime(&ms, p.events[0], p.events[1]));
   const double steps = (double)(p.h_ctr->lane_steps - before);
   *rate = ms > 0.f ? steps / (ms * 1e-3) : 0.0;
+  *slot_rate = *rate / (double)(lanes * (uint64_t)R);
   return FPT_OK;
 }
 
@@ -145,7 +152,7 @@ fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
       if (need_r) t.replicas_per_lane = cached.replicas_per_lane;
       if (need_w) t.waves_per_simd = cached.waves_per_simd;
       best = cached;
-      have_rate = cached.slot_steps_per_s > 0;
+      have_rate = cached.per_slot_steps_per_s > 0;
     } else if (total_replicas > 0) {
       std::vector<int> rs = need_r ? std::vector<int>{1, 2}
                                    : std::vector<int>{t.replicas_per_lane};
@@ -158,13 +165,14 @@ fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
           fpt_tuning c = t;
           c.replicas_per_lane = r;
           c.waves_per_simd = w;
-          double rate = 0.0;
-          FPT_TRY(trial(*this, ws, st, c, &rate));
+          double rate = 0.0, slot_rate = 0.0;
+          FPT_TRY(trial(*this, ws, st, c, &rate, &slot_rate));
           if (rate > best_rate) {
             best_rate = rate;
             best.replicas_per_lane = r;
             best.waves_per_simd = w;
             best.slot_steps_per_s = rate;
+            best.per_slot_steps_per_s = slot_rate;
           }
         }
       }
@@ -180,10 +188,8 @@ fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
   if (t.waves_per_simd == 0) t.waves_per_simd = kMaxWavesPerSimd;
   if (need_s) {
     uint64_t s = 16384;
-    if (have_rate) {
-      const double slots = (double)(lanes_for(t) * (uint64_t)t.replicas_per_lane);
-      s = (uint64_t)(launch_ms_target() * 1e-3 * best.slot_steps_per_s / slots);
-    }
+    if (have_rate && best.per_slot_steps_per_s > 0)
+      s = (uint64_t)(launch_ms_target() * 1e-3 * best.per_slot_steps_per_s);
     s = std::max<uint64_t>(256, std::min<uint64_t>(s, uint64_t(1) << 20));
     t.steps_per_launch = (int32_t)(s / 4 * 4);
   }

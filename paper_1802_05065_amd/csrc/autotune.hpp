@@ -11,6 +11,7 @@ struct TuneEntry {
   int replicas_per_lane = 1;
   int waves_per_simd = 8;
   double slot_steps_per_s = 0.0;  // measured issue rate of the winning shape
+  double per_slot_steps_per_s = 0.0;  // the same per resident slot
 };
 
 // Key: GPU architecture, precision, model, schedule and set-count bucket.

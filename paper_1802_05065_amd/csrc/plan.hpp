@@ -44,6 +44,7 @@ struct Plan {
   Counters* h_ctr = nullptr;    // pinned
   std::vector<hipEvent_t> events;
   hipGraphExec_t graph_exec = nullptr;
+  hipStream_t graph_stream = nullptr;  // capture / replay stream of the graph path
 
   ~Plan();
   fpt_status layout();

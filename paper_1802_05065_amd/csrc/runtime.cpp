@@ -212,6 +212,7 @@ Plan::~Plan() {
   if (h_ctr) (void)hipHostFree(h_ctr);
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph_stream) (void)hipStreamDestroy(graph_stream);
 }
 
 fpt_status Plan::ensure_host_resources(size_t n_events) {
@@ -310,21 +311,28 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
   size_t ev_used = 0;
 
   if (tuning.use_graph && !finished) {
-    // capture a fixed group of launches plus the status copy once, replay it
+    // A fixed group of launches plus the status copy is captured once on a
+    // plan-owned stream (the legacy NULL stream cannot be captured) and
+    // replayed; events order it after earlier work on `st` and order later
+    // work on `st` after it.
     group = 8;
-    FPT_TRY(ensure_host_resources(2 + 1));
+    FPT_TRY(ensure_host_resources(4));
+    if (!graph_stream) FPT_HIP(hipStreamCreateWithFlags(&graph_stream, hipStreamNonBlocking));
+    FPT_HIP(hipEventRecord(events[2], st));
+    FPT_HIP(hipStreamWaitEvent(graph_stream, events[2], 0));
     if (graph_exec) {
       (void)hipGraphExecDestroy(graph_exec);
       graph_exec = nullptr;
     }
     hipGraph_t g = nullptr;
-    FPT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    FPT_HIP(hipStreamBeginCapture(graph_stream, hipStreamCaptureModeThreadLocal));
     hipError_t cap_err = hipSuccess;
     for (int i = 0; i < group && cap_err == hipSuccess; ++i)
-      cap_err = launch_slice(fp64, model, R, multi, a, groups, st);
+      cap_err = launch_slice(fp64, model, R, multi, a, groups, graph_stream);
     if (cap_err == hipSuccess)
-      cap_err = hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st);
-    hipError_t end_err = hipStreamEndCapture(st, &g);
+      cap_err = hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
+                               graph_stream);
+    hipError_t end_err = hipStreamEndCapture(graph_stream, &g);
     if (cap_err != hipSuccess || end_err != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
       return fail(FPT_E_DEVICE, "graph capture failed: %s",
@@ -335,9 +343,9 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
     if (inst != hipSuccess)
       return fail(FPT_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(inst));
     while (!finished) {
-      FPT_HIP(hipEventRecord(events[0], st));
-      FPT_HIP(hipGraphLaunch(graph_exec, st));
-      FPT_HIP(hipEventRecord(events[1], st));
+      FPT_HIP(hipEventRecord(events[0], graph_stream));
+      FPT_HIP(hipGraphLaunch(graph_exec, graph_stream));
+      FPT_HIP(hipEventRecord(events[1], graph_stream));
       FPT_HIP(hipEventSynchronize(events[1]));
       float ms = 0.f;
       FPT_HIP(hipEventElapsedTime(&ms, events[0], events[1]));
@@ -348,6 +356,8 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
         return fail(FPT_E_DEVICE, "run did not finish within %llu launches",
                     (unsigned long long)bound);
     }
+    FPT_HIP(hipEventRecord(events[3], graph_stream));
+    FPT_HIP(hipStreamWaitEvent(st, events[3], 0));
   } else {
     while (!finished) {
       FPT_TRY(ensure_host_resources(ev_used + 2 * group + 1));
