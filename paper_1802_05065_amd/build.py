@@ -16,6 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfpt.so")
+ISA_RATES = os.path.join(HERE, "isa_rates")
 
 SOURCES = ["kernels.hip", "runtime.cpp", "autotune.cpp", "server.cpp"]
 
@@ -55,6 +56,11 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    # issue-rate microbenchmark of the instructions the integrator uses
+    res = subprocess.run([HIPCC, *COMMON, *DEVICE, os.path.join(CSRC, "isa_rates.hip"),
+                          "-o", ISA_RATES], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"isa_rates build failed:\n{res.stdout}\n{res.stderr}")
     if verbose:
         print("built", LIB)
     return LIB

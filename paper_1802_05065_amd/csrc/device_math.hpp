@@ -18,8 +18,8 @@ namespace fpt {
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The 32x32 -> 64
-// products map to v_mad_u64_u32; with a wave-uniform key the key schedule
-// lives in scalar registers.
+// products map to v_mad_u64_u32, the XOR pairs to gfx950's v_bitop3_b32; with
+// a wave-uniform key the key schedule lives in scalar registers.
 struct Words {
   uint32_t w0, w1, w2, w3;
 };
@@ -31,8 +31,9 @@ __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1,
   for (int round = 0; round < 10; ++round) {
     const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)c0;
     const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-    const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    // three-input XOR in one v_bitop3_b32 (truth table 0x96)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c3, k1, 0x96);
     c1 = (uint32_t)pb;
     c3 = (uint32_t)pa;
     c0 = n0;
@@ -73,19 +74,40 @@ __device__ __forceinline__ void normals_f64(const Words& w, double z[4]) {
   }
 }
 
-// FP32: hardware transcendentals.  v_log_f32 is log2, v_sin/v_cos_f32 take
-// their argument in revolutions, so 2 pi b needs no multiply.
-__device__ __forceinline__ void normals_f32(const Words& w, float z[4]) {
+// FP32: hardware transcendentals.  v_log_f32 is log2 and v_sin/v_cos_f32 take
+// their argument in revolutions, so 2 pi b needs no multiply.  The integrator
+// uses the pair in factored form: radius' = sqrt(-log2 a) and the angle's
+// cos / sin, with the constant sqrt(2 ln 2) folded into its noise scale, so
+// z = sqrt(2 ln 2) radius' (cos, sin).
+constexpr float kSqrt2Ln2 = 1.1774100225154747f;
+
+struct BoxMullerF32 {
+  float radius[2];  // sqrt(-log2 a) of pairs (w0, w1) and (w2, w3)
+  float c[2], s[2];
+};
+
+__device__ __forceinline__ BoxMullerF32 box_muller_f32(const Words& w) {
   const uint32_t x[4] = {w.w0, w.w1, w.w2, w.w3};
+  BoxMullerF32 bm;
 #pragma unroll
   for (int pair = 0; pair < 2; ++pair) {
     const float a = __builtin_fmaf((float)x[2 * pair], 0x1p-32f, 0x1p-33f);
-    const float b = __builtin_fmaf((float)x[2 * pair + 1], 0x1p-32f, 0x1p-33f);
-    // -2 ln a = -2 ln(2) log2(a)
-    const float radius =
-        __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(a));
-    z[2 * pair] = radius * __builtin_amdgcn_cosf(b);
-    z[2 * pair + 1] = radius * __builtin_amdgcn_sinf(b);
+    const float b = (float)x[2 * pair + 1] * 0x1p-32f;
+    bm.radius[pair] = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(a));
+    bm.c[pair] = __builtin_amdgcn_cosf(b);
+    bm.s[pair] = __builtin_amdgcn_sinf(b);
+  }
+  return bm;
+}
+
+// The four standard normals of a block in FP32 (diagnostics).
+__device__ __forceinline__ void normals_f32(const Words& w, float z[4]) {
+  const BoxMullerF32 bm = box_muller_f32(w);
+#pragma unroll
+  for (int pair = 0; pair < 2; ++pair) {
+    const float r = kSqrt2Ln2 * bm.radius[pair];
+    z[2 * pair] = r * bm.c[pair];
+    z[2 * pair + 1] = r * bm.s[pair];
   }
 }
 
@@ -96,9 +118,14 @@ struct ParF64 {
   double gamma0, dgamma, dt, alpha, V0, sigma, th;
 };
 
+// FP32C constants, phase in revolutions (phi / 2 pi):
+//   underdamped  v_k = damp v + G_k - kS sin(2 pi phr) + sig z_k,
+//                phr_k = phr + h_rev v            (Kahan-compensated)
+//   overdamped   phr_k = phr + G_k - kS sin(2 pi phr) + sig z_k  (compensated)
+// with G_k = gA + gB k evaluated in FP64 from the exact step k.
 struct ParF32 {
-  double gamma0, dgamma, th;
-  float h, damp, hV0, sigma, V0, th_near;
+  double gA, gB, th_rev;
+  float h_rev, damp, kS, sig, dG, th_near_rev;
 };
 
 __device__ __forceinline__ ParF64 load_par_f64(const SetDev& s) {
@@ -106,8 +133,8 @@ __device__ __forceinline__ ParF64 load_par_f64(const SetDev& s) {
 }
 
 __device__ __forceinline__ ParF32 load_par_f32(const SetDev& s) {
-  return ParF32{s.gamma0, s.dgamma, s.th, s.h_f, s.damp_f,
-                s.hV0_f, s.sigma_f, s.V0_f, s.th_near_f};
+  return ParF32{s.gA, s.gB, s.th_rev, s.h_rev_f, s.damp_f, s.kS_f, s.sig_f, s.dG_f,
+                s.th_near_rev_f};
 }
 
 // ---------------------------------------------------------------------------
@@ -135,42 +162,43 @@ __device__ __forceinline__ void step_f64_over(const ParF64& p, double kd,
   phi = phi + p.dt * drift + p.sigma * r;
 }
 
-// FP32C underdamped.  The phase is the compensated pair (phi, c) with true
-// value phi - c (Kahan summation of the increments dt v); gamma_k comes from
-// the exact step count in FP64 and is rounded once to FP32.
-//   v_k = (1 - h alpha) v + h V0 (gamma_k - sin phi) + sigma r
-__device__ __forceinline__ void step_f32_under(const ParF32& p, double kd,
-                                               float r, float& phi, float& c,
+// FP32C underdamped step q (0..3) of a block.  The phase is the compensated
+// pair (phr, c) in revolutions with true value phr - c (Kahan summation of the
+// increments h_rev v); `g` is G_k rounded once to FP32; `zs` is the noise
+// factor sig*radius' and `trig` the cos or sin of the pair's angle.
+__device__ __forceinline__ void step_f32_under(const ParF32& p, float g, float zs,
+                                               float trig, float& phr, float& c,
                                                float& v) {
-  const float gamma_k = (float)__builtin_fma(p.dgamma, kd, p.gamma0);
-  const float s = __builtin_amdgcn_sinf(phi * 0.15915494309189535f);
-  // Kahan: y = h v - c; t = phi + y; c = (t - phi) - y; phi = t
-  const float y = __builtin_fmaf(p.h, v, -c);
-  const float t = phi + y;
-  c = (t - phi) - y;
-  phi = t;
-  const float kick = __builtin_fmaf(p.sigma, r, p.damp * v);
-  v = __builtin_fmaf(p.hV0, gamma_k - s, kick);
+  const float s = __builtin_amdgcn_sinf(phr);
+  const float y = __builtin_fmaf(p.h_rev, v, -c);
+  const float t = phr + y;
+  c = (t - phr) - y;
+  phr = t;
+  const float inc = __builtin_fmaf(-p.kS, s, __builtin_fmaf(zs, trig, g));
+  v = __builtin_fmaf(p.damp, v, inc);
 }
 
-// FP32C overdamped: the increment y = h (gamma_k - V0 sin phi) + sigma r is
-// added to the compensated phase (phi, c).
-__device__ __forceinline__ void step_f32_over(const ParF32& p, double kd,
-                                              float r, float& phi, float& c) {
-  const float gamma_k = (float)__builtin_fma(p.dgamma, kd, p.gamma0);
-  const float s = __builtin_amdgcn_sinf(phi * 0.15915494309189535f);
-  const float drift = __builtin_fmaf(-p.V0, s, gamma_k);
-  const float y = __builtin_fmaf(p.h, drift, __builtin_fmaf(p.sigma, r, -c));
-  const float t = phi + y;
-  c = (t - phi) - y;
-  phi = t;
+// FP32C overdamped: the increment G_k - kS sin(2 pi phr) + sig z_k is added
+// to the compensated phase.
+__device__ __forceinline__ void step_f32_over(const ParF32& p, float g, float zs,
+                                              float trig, float& phr, float& c) {
+  const float s = __builtin_amdgcn_sinf(phr);
+  const float inc = __builtin_fmaf(-p.kS, s, __builtin_fmaf(zs, trig, g));
+  const float y = inc - c;
+  const float t = phr + y;
+  c = (t - phr) - y;
+  phr = t;
 }
 
-// Test of the compensated phase against the FP64 threshold: phi - c formed
-// in FP64 holds the compensated value to FP64 rounding (exactly whenever c is
-// within 2^-29 of phi's magnitude, the usual case after a Kahan update).
-__device__ __forceinline__ bool above_f64(float phi, float c, double th) {
-  return ((double)phi - (double)c) > th;
+// G_k of the block's first step, from the exact step count k1 = 4 j + 1.
+__device__ __forceinline__ float block_g_f32(const ParF32& p, double k1) {
+  return (float)__builtin_fma(p.gB, k1, p.gA);
+}
+
+// Test of the compensated phase against the FP64 threshold (revolutions):
+// phr - c formed in FP64 holds the compensated value to FP64 rounding.
+__device__ __forceinline__ bool above_f64(float phr, float c, double th_rev) {
+  return ((double)phr - (double)c) > th_rev;
 }
 
 }  // namespace fpt

@@ -23,8 +23,10 @@ constexpr int kBinBits = 12;       // FPT_MAX_BINS = 1 << kBinBits
 // Per-set constants, derived on the host (Algorithm 1 / 3 preamble).
 struct alignas(16) SetDev {
   double gamma0, dgamma, dt, alpha, V0, sigma, th, phi0, v0;
-  // FP32C copies: h, (1 - h alpha), h V0, sigma, th rounded down by a margin
-  float h_f, damp_f, hV0_f, sigma_f, V0_f, th_near_f, phi0_f, c0_f, v0_f, pad_f;
+  // FP32C constants (phase in revolutions, phi / 2 pi): bias term
+  // G_k = gA + gB k in FP64, threshold, and FP32 step coefficients
+  double gA, gB, th_rev;
+  float h_rev_f, damp_f, kS_f, sig_f, dG_f, th_near_rev_f, phr0_f, c0_f, v0_f, pad_f;
   int64_t max_steps;    // klim
   uint64_t jmax;        // block of the last allowed step: (max_steps - 1) / 4
   int64_t k_hist;       // histogram covers steps [1, k_hist]

@@ -53,8 +53,8 @@ struct Slot<false> {
   uint32_t set;
   uint64_t idx, j;
   double kd;
-  float phi, v;
-  float c;
+  float phi, v;  // phi: phase in revolutions
+  float c;       // its Kahan compensation
   ParF32 p;
   uint32_t k0, k1;
   uint64_t jmax;
@@ -84,7 +84,7 @@ __device__ __forceinline__ void start_replica(Slot<FP64>& s, uint32_t set,
     s.v = sd.v0;
     s.c = 0.0f;
   } else {
-    s.phi = sd.phi0_f;
+    s.phi = sd.phr0_f;
     s.c = sd.c0_f;
     s.v = sd.v0_f;
   }
@@ -393,16 +393,14 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
 
     // ---- 4 Euler steps per slot
     uint64_t esc[R][4];
+    if constexpr (FP64) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      Slot<FP64>& sl = s[r];
-      const auto& p = MULTI ? sl.p : uni.p;
-      const uint32_t k0 = MULTI ? sl.k0 : uni.k0;
-      const uint32_t k1 = MULTI ? sl.k1 : uni.k1;
-      const Words w = philox4x32_10((uint32_t)sl.j, (uint32_t)(sl.j >> 32),
-                                    (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32),
-                                    k0, k1);
-      if constexpr (FP64) {
+      for (int r = 0; r < R; ++r) {
+        Slot<FP64>& sl = s[r];
+        const auto& p = MULTI ? sl.p : uni.p;
+        const Words w = philox4x32_10((uint32_t)sl.j, (uint32_t)(sl.j >> 32),
+                                      (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32),
+                                      MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
         double z[4];
         normals_f64(w, z);
 #pragma unroll
@@ -415,20 +413,54 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
           }
           esc[r][q] = __ballot(sl.phi > p.th);
         }
-      } else {
-        float z[4];
-        normals_f32(w, z);
+      }
+    } else {
+      // generator and normals of every slot first, then the 4 steps with the
+      // slots interleaved (independent chains for the scheduler)
+      BoxMullerF32 bm[R];
+      float g0[R], zs[R][2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double kd = sl.kd + (double)(q + 1);
+      for (int r = 0; r < R; ++r) {
+        Slot<FP64>& sl = s[r];
+        const auto& p = MULTI ? sl.p : uni.p;
+        const Words w = philox4x32_10((uint32_t)sl.j, (uint32_t)(sl.j >> 32),
+                                      (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32),
+                                      MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
+        bm[r] = box_muller_f32(w);
+        g0[r] = block_g_f32(p, sl.kd + 1.0);
+        zs[r][0] = p.sig * bm[r].radius[0];
+        zs[r][1] = p.sig * bm[r].radius[1];
+      }
+      float ph_q[R][4], c_q[R][4];
+      uint64_t near[R][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          Slot<FP64>& sl = s[r];
+          const auto& p = MULTI ? sl.p : uni.p;
+          const float g = q == 0 ? g0[r] : __builtin_fmaf(p.dG, (float)q, g0[r]);
+          const float trig = (q & 1) ? bm[r].s[q >> 1] : bm[r].c[q >> 1];
           if constexpr (MODEL == FPT_UNDERDAMPED) {
-            step_f32_under(p, kd, z[q], sl.phi, sl.c, sl.v);
+            step_f32_under(p, g, zs[r][q >> 1], trig, sl.phi, sl.c, sl.v);
           } else {
-            step_f32_over(p, kd, z[q], sl.phi, sl.c);
+            step_f32_over(p, g, zs[r][q >> 1], trig, sl.phi, sl.c);
           }
-          const uint64_t near = __ballot(sl.phi > p.th_near);
-          esc[r][q] = near ? __ballot(above_f64(sl.phi, sl.c, p.th)) : 0ull;
+          ph_q[r][q] = sl.phi;
+          c_q[r][q] = sl.c;
+          near[r][q] = __ballot(sl.phi > p.th_near_rev);
         }
+      }
+      // exact FP64 test only where a lane came near the threshold
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const auto& p = MULTI ? s[r].p : uni.p;
+        const uint64_t any_near = near[r][0] | near[r][1] | near[r][2] | near[r][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          esc[r][q] = any_near ? (__ballot(above_f64(ph_q[r][q], c_q[r][q], p.th_rev)) &
+                                  near[r][q])
+                               : 0ull;
       }
     }
 
@@ -588,16 +620,18 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
         out_v[k0 + q] = s.v;
       }
     } else {
-      float z[4];
-      normals_f32(w, z);
+      const BoxMullerF32 bm = box_muller_f32(w);
+      const float g0 = block_g_f32(s.p, s.kd + 1.0);
       for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
-        const double kd = s.kd + (double)(q + 1);
+        const float g = q == 0 ? g0 : __builtin_fmaf(s.p.dG, (float)q, g0);
+        const float zs = s.p.sig * bm.radius[q >> 1];
+        const float trig = (q & 1) ? bm.s[q >> 1] : bm.c[q >> 1];
         if constexpr (MODEL == FPT_UNDERDAMPED) {
-          step_f32_under(s.p, kd, z[q], s.phi, s.c, s.v);
+          step_f32_under(s.p, g, zs, trig, s.phi, s.c, s.v);
         } else {
-          step_f32_over(s.p, kd, z[q], s.phi, s.c);
+          step_f32_over(s.p, g, zs, trig, s.phi, s.c);
         }
-        out_phi[k0 + q] = (double)s.phi - (double)s.c;
+        out_phi[k0 + q] = 2.0 * kPi * ((double)s.phi - (double)s.c);
         out_v[k0 + q] = (double)s.v;
       }
     }

@@ -90,18 +90,35 @@ SetDev derive_set(const fpt_params& p) {
   s.v0 = std::isnan(p.v0) ? 0.0 : p.v0;
   // default threshold: top of the washboard barrier, pi - arcsin(gamma)
   s.th = std::isnan(p.threshold) ? 3.14159265358979323846 - s.phi0 : p.threshold;
-  s.h_f = (float)p.dt;
-  s.damp_f = (float)(1.0 - p.dt * p.alpha);
-  s.hV0_f = (float)(p.dt * p.V0);
-  s.sigma_f = (float)s.sigma;
-  s.V0_f = (float)p.V0;
-  // below th_near_f the compensated phase cannot exceed th: 8 float ulps of
-  // margin cover the compensation term and the rounding of th itself
-  float tn = round_toward_minus_inf(s.th);
+  // FP32C: phase in revolutions so v_sin_f32 takes it directly; the
+  // Box-Muller constant sqrt(2 ln 2) goes into the noise scale
+  const double twopi = 2.0 * 3.14159265358979323846;
+  const double sqrt2ln2 = 1.1774100225154747;
+  if (p.model == FPT_UNDERDAMPED) {
+    s.gA = p.dt * p.V0 * p.gamma0;     // G_k = h V0 gamma_k
+    s.gB = p.dt * p.V0 * s.dgamma;
+    s.kS_f = (float)(p.dt * p.V0);
+    s.sig_f = (float)(s.sigma * sqrt2ln2);
+    s.h_rev_f = (float)(p.dt / twopi);
+    s.damp_f = (float)(1.0 - p.dt * p.alpha);
+  } else {
+    s.gA = p.dt * p.gamma0 / twopi;    // G_k = h gamma_k / 2 pi
+    s.gB = p.dt * s.dgamma / twopi;
+    s.kS_f = (float)(p.dt * p.V0 / twopi);
+    s.sig_f = (float)(s.sigma * sqrt2ln2 / twopi);
+    s.h_rev_f = 0.0f;
+    s.damp_f = 1.0f;
+  }
+  s.dG_f = (float)s.gB;
+  s.th_rev = s.th / twopi;
+  // at or below th_near_rev_f the compensated phase cannot exceed th_rev:
+  // 8 float ulps of margin cover the compensation term and the rounding
+  float tn = round_toward_minus_inf(s.th_rev);
   for (int i = 0; i < 8; ++i) tn = std::nextafter(tn, -INFINITY);
-  s.th_near_f = tn;
-  s.phi0_f = (float)s.phi0;
-  s.c0_f = (float)((double)s.phi0_f - s.phi0);
+  s.th_near_rev_f = tn;
+  const double phr0 = s.phi0 / twopi;
+  s.phr0_f = (float)phr0;
+  s.c0_f = (float)((double)s.phr0_f - phr0);
   s.v0_f = (float)s.v0;
   s.max_steps = p.max_steps;
   s.jmax = (uint64_t)(p.max_steps - 1) / 4;
