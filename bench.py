@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--replicas", type=int, default=2 ** 20,
                     help="replicas of the FP32C leg (the workload has 2^20)")
     ap.add_argument("--fp64-replicas", type=int, default=2 ** 18,
-                    help="replicas of the FP64 comparison leg (independent seed)")
+                    help="replicas of the FP64 comparison leg (independent seed); 0 runs "
+                         "the FP32C leg alone and prints its figures only")
     ap.add_argument("--cpu-replicas", type=int, default=32,
                     help="replicas of the oracle CPU-baseline sample (0: skip)")
     ap.add_argument("--cpu-procs", type=int, default=0,
@@ -128,6 +129,8 @@ def main():
     # same size and shape with a 1000x faster ramp, so the tuner sees the
     # real occupancy
     for prec, n in (("fp32c", args.replicas), ("fp64", args.fp64_replicas)):
+        if n <= 0:
+            continue
         api.simulate(workloads.switching_ramp(n_replicas=n, seed=99) | dict(
             ramp=1e-3, max_steps=20_100, hist_k_max=20_000), prec, record_steps=False)
 
@@ -149,6 +152,12 @@ def main():
     steps32 = last.steps[0].cpu().numpy()
     print(f"[bench] fp32c {args.replicas} replicas: {value:.4e} replica-steps/s, "
           f"{st['n_launches']} launches, tuning {st['tuning']}", file=sys.stderr, flush=True)
+
+    if args.fp64_replicas <= 0:  # profiling runs: the FP32C leg only
+        print(json.dumps({"value": value, "launches": st["n_launches"],
+                          "kernel_ms": st["kernel_ms"], "replica_steps": st["replica_steps"],
+                          "tuning": st["tuning"]}), flush=True)
+        return
 
     # FP64 leg (independent seed) for the speed ratio and the KS test
     p64 = workloads.switching_ramp(n_replicas=args.fp64_replicas, seed=3)

@@ -1,12 +1,15 @@
 // isa_rates.hip -- issue-rate microbenchmark of the VALU instructions the
-// integrator is made of (gfx950).  Each thread runs 8 independent dependency
-// chains of one operation; with 8 waves per SIMD the chains hide latency, so
-// the measured rate is the throughput.  Rates are reported relative to a
-// chain of v_fma_f32, the full-rate reference, which gives each instruction's
-// cost in full-rate issue slots.  A "pair" test interleaves v_fma_f32 with a
-// transcendental to show whether the two share issue slots.
+// integrator is built from (gfx950).
 //
-// usage: isa_rates  (prints one line per operation)
+// Each lane runs 8 independent dependency chains of one instruction, written
+// as inline assembly so that the compiler neither folds nor reorders them;
+// with 8 waves per SIMD the chains hide latency and the measured rate is the
+// instruction's throughput.  Rates are printed absolute (lane-ops/s) and
+// relative to v_fma_f32, i.e. each instruction's cost in v_fma_f32 issue
+// slots.  "pair" tests issue two different instructions per chain step to
+// show whether they overlap (cost of the pair < sum of the two).
+//
+// usage: isa_rates
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -22,90 +25,81 @@
   } while (0)
 
 constexpr int kChains = 8;
-constexpr int kIters = 2048;
+constexpr int kIters = 1024;
 constexpr int kThreads = 256;
 
-enum Op {
-  OP_FMA_F32, OP_SIN_F32, OP_LOG_F32, OP_SQRT_F32, OP_MAD_U64_U32, OP_MUL_HI_U32,
-  OP_XOR, OP_FMA_F64, OP_CVT_F32_F64, OP_CVT_F32_U32, OP_PAIR_FMA_SIN, OP_PAIR_FMA_MAD64,
-  OP_COUNT
+// One chain step per op.  Operands: x, y (32-bit chains), d (64-bit chain),
+// a, b (64-bit constants) and p, q (32-bit constants).
+#define OP_LIST(X)                                                                     \
+  X(fma_f32, "v_fma_f32 %[x], %[x], %[p], %[q]", 1)                                   \
+  X(add_f32, "v_add_f32 %[x], %[x], %[p]", 1)                                         \
+  X(mul_f32, "v_mul_f32 %[x], %[x], %[p]", 1)                                         \
+  X(sin_f32, "v_sin_f32 %[x], %[x]", 1)                                               \
+  X(cos_f32, "v_cos_f32 %[x], %[x]", 1)                                               \
+  X(log_f32, "v_log_f32 %[x], %[x]", 1)                                               \
+  X(sqrt_f32, "v_sqrt_f32 %[x], %[x]", 1)                                             \
+  X(cvt_f32_u32, "v_cvt_f32_u32 %[x], %[x]", 1)                                       \
+  X(xor_b32, "v_xor_b32 %[x], %[x], %[p]", 1)                                         \
+  X(bitop3_b32, "v_bitop3_b32 %[x], %[x], %[p], %[q] bitop3:0x96", 1)                 \
+  X(add_u32, "v_add_u32 %[x], %[x], %[p]", 1)                                         \
+  X(mul_lo_u32, "v_mul_lo_u32 %[x], %[x], %[p]", 1)                                   \
+  X(mul_hi_u32, "v_mul_hi_u32 %[x], %[x], %[p]", 1)                                   \
+  X(fma_f64, "v_fma_f64 %[d], %[d], %[a], %[b]", 1)                                   \
+  X(add_f64, "v_add_f64 %[d], %[d], %[a]", 1)                                         \
+  X(mad_u64_u32, "v_mad_u64_u32 %[d], vcc, %[x], %[p], %[d]", 1)                      \
+  X(cvt_f32_f64_pair, "v_cvt_f32_f64 %[x], %[d]\n v_cvt_f64_f32 %[d], %[x]", 2)       \
+  X(fma_f32_sin, "v_fma_f32 %[x], %[x], %[p], %[q]\n v_sin_f32 %[y], %[y]", 2)        \
+  X(fma_f32_mulhi, "v_fma_f32 %[x], %[x], %[p], %[q]\n v_mul_hi_u32 %[y], %[y], %[p]", 2) \
+  X(fma_f32_fma_f64, "v_fma_f64 %[d], %[d], %[a], %[b]\n v_fma_f32 %[x], %[x], %[p], %[q]", 2) \
+  X(fma_f32_mad64, "v_mad_u64_u32 %[d], vcc, %[y], %[p], %[d]\n v_fma_f32 %[x], %[x], %[p], %[q]", 2) \
+  X(sin_mad64, "v_mad_u64_u32 %[d], vcc, %[y], %[p], %[d]\n v_sin_f32 %[x], %[x]", 2)
+
+#define DECL(name, text, n)                                                           \
+  __global__ __launch_bounds__(kThreads) void k_##name(float* out, float seed) {     \
+    const uint32_t t = blockIdx.x * kThreads + threadIdx.x;                           \
+    float x[kChains], y[kChains];                                                     \
+    double d[kChains];                                                                \
+    const double a = 0.999 + 1e-9 * seed, b = 1e-3 * seed;                            \
+    const float p = 0.999f + 1e-9f * seed, q = 1e-3f * seed;                          \
+    for (int c = 0; c < kChains; ++c) {                                               \
+      x[c] = 0.25f + 1e-7f * (float)(t + c);                                          \
+      y[c] = 0.5f + 1e-7f * (float)(t + c);                                           \
+      d[c] = 0.25 + 1e-7 * (double)(t + c);                                           \
+    }                                                                                 \
+    for (int i = 0; i < kIters; ++i) {                                                \
+      _Pragma("unroll") for (int c = 0; c < kChains; ++c)                             \
+        asm volatile(text : [x] "+v"(x[c]), [y] "+v"(y[c]), [d] "+v"(d[c])            \
+                     : [a] "v"(a), [b] "v"(b), [p] "v"(p), [q] "v"(q) : "vcc");       \
+    }                                                                                 \
+    float acc = 0.f;                                                                  \
+    for (int c = 0; c < kChains; ++c) acc += x[c] + y[c] + (float)d[c];               \
+    out[t] = acc;                                                                     \
+  }
+
+OP_LIST(DECL)
+
+struct Entry {
+  const char* name;
+  void (*kernel)(float*, float);
+  int insts;
+  double rate;  // chain steps per second (all lanes)
 };
 
-static const char* kNames[OP_COUNT] = {
-    "v_fma_f32", "v_sin_f32", "v_log_f32", "v_sqrt_f32", "v_mad_u64_u32 (+xor)",
-    "v_mul_hi_u32 (+add)", "v_xor_b32", "v_fma_f64", "v_cvt_f32_f64 (+fma_f64)",
-    "v_cvt_f32_u32 (+add)",
-    "v_fma_f32 + v_sin_f32 (pair)", "v_fma_f32 + v_mad_u64_u32 (pair)"};
-// VALU instructions per chain step (the v_mad_u64_u32 step also xors the two
-// halves; the conversions come with one add)
-static const int kInstPerStep[OP_COUNT] = {1, 1, 1, 1, 2, 2, 1, 1, 2, 2, 2, 3};
+#define ENTRY(name, text, n) {#name, k_##name, n, 0.0},
+static Entry g_entries[] = {OP_LIST(ENTRY)};
 
-template <int OP>
-__global__ __launch_bounds__(kThreads) void rate_kernel(float* out, float seed) {
-  const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
-  float f[kChains], g[kChains];
-  double d[kChains];
-  uint32_t u[kChains];
-  for (int c = 0; c < kChains; ++c) {
-    f[c] = seed * (float)(t + c + 1) * 1e-9f;
-    g[c] = f[c] + 0.25f;
-    d[c] = (double)f[c];
-    u[c] = t * 2654435761u + (uint32_t)c;
-  }
-  for (int i = 0; i < kIters; ++i) {
-#pragma unroll
-    for (int c = 0; c < kChains; ++c) {
-      if constexpr (OP == OP_FMA_F32) {
-        f[c] = __builtin_fmaf(f[c], 0.999f, 1e-3f);
-      } else if constexpr (OP == OP_SIN_F32) {
-        f[c] = __builtin_amdgcn_sinf(f[c]);
-      } else if constexpr (OP == OP_LOG_F32) {
-        f[c] = __builtin_amdgcn_logf(f[c]);
-      } else if constexpr (OP == OP_SQRT_F32) {
-        f[c] = __builtin_amdgcn_sqrtf(f[c]);
-      } else if constexpr (OP == OP_MAD_U64_U32) {
-        const uint64_t p = (uint64_t)u[c] * 0xD2511F53u;
-        u[c] = (uint32_t)p ^ (uint32_t)(p >> 32);
-      } else if constexpr (OP == OP_MUL_HI_U32) {
-        u[c] = __umulhi(u[c], 0xCD9E8D57u) + 1u;
-      } else if constexpr (OP == OP_XOR) {
-        u[c] ^= (uint32_t)i * 0x9E3779B9u;
-      } else if constexpr (OP == OP_FMA_F64) {
-        d[c] = __builtin_fma(d[c], 0.999, 1e-3);
-      } else if constexpr (OP == OP_CVT_F32_F64) {
-        f[c] = (float)d[c];
-        d[c] = __builtin_fma(d[c], 0.999, 1e-3);
-      } else if constexpr (OP == OP_CVT_F32_U32) {
-        f[c] = (float)(u[c] + (uint32_t)__float_as_uint(f[c]));
-      } else if constexpr (OP == OP_PAIR_FMA_SIN) {
-        f[c] = __builtin_fmaf(f[c], 0.999f, 1e-3f);
-        g[c] = __builtin_amdgcn_sinf(g[c]);
-      } else if constexpr (OP == OP_PAIR_FMA_MAD64) {
-        f[c] = __builtin_fmaf(f[c], 0.999f, 1e-3f);
-        const uint64_t p = (uint64_t)u[c] * 0xD2511F53u;
-        u[c] = (uint32_t)p ^ (uint32_t)(p >> 32);
-      }
-    }
-  }
-  float acc = 0.f;
-  for (int c = 0; c < kChains; ++c) acc += f[c] + g[c] + (float)d[c] + (float)u[c];
-  out[t] = acc;
-}
-
-template <int OP>
-static int run(float* out, int groups, hipEvent_t e0, hipEvent_t e1, double* ops_per_s) {
-  hipLaunchKernelGGL(rate_kernel<OP>, dim3(groups), dim3(kThreads), 0, 0, out, 1.0f);
+static int measure(Entry& e, float* out, int groups, hipEvent_t e0, hipEvent_t e1) {
+  hipLaunchKernelGGL(e.kernel, dim3(groups), dim3(kThreads), 0, 0, out, 1.0f);
   CHECK(hipGetLastError());
   CHECK(hipEventRecord(e0, 0));
-  for (int rep = 0; rep < 5; ++rep)
-    hipLaunchKernelGGL(rate_kernel<OP>, dim3(groups), dim3(kThreads), 0, 0, out, 1.0f);
+  for (int rep = 0; rep < 4; ++rep)
+    hipLaunchKernelGGL(e.kernel, dim3(groups), dim3(kThreads), 0, 0, out, 1.0f);
   CHECK(hipGetLastError());
   CHECK(hipEventRecord(e1, 0));
   CHECK(hipEventSynchronize(e1));
   float ms = 0.f;
   CHECK(hipEventElapsedTime(&ms, e0, e1));
-  const double lane_steps = 5.0 * groups * kThreads * (double)kIters * kChains;
-  *ops_per_s = lane_steps / (ms * 1e-3);
+  e.rate = 4.0 * groups * kThreads * (double)kIters * kChains / (ms * 1e-3);
   return 0;
 }
 
@@ -119,29 +113,19 @@ int main() {
   hipEvent_t e0, e1;
   CHECK(hipEventCreate(&e0));
   CHECK(hipEventCreate(&e1));
-  double r[OP_COUNT];
-  if (run<OP_FMA_F32>(out, groups, e0, e1, &r[OP_FMA_F32]) ||
-      run<OP_SIN_F32>(out, groups, e0, e1, &r[OP_SIN_F32]) ||
-      run<OP_LOG_F32>(out, groups, e0, e1, &r[OP_LOG_F32]) ||
-      run<OP_SQRT_F32>(out, groups, e0, e1, &r[OP_SQRT_F32]) ||
-      run<OP_MAD_U64_U32>(out, groups, e0, e1, &r[OP_MAD_U64_U32]) ||
-      run<OP_MUL_HI_U32>(out, groups, e0, e1, &r[OP_MUL_HI_U32]) ||
-      run<OP_XOR>(out, groups, e0, e1, &r[OP_XOR]) ||
-      run<OP_FMA_F64>(out, groups, e0, e1, &r[OP_FMA_F64]) ||
-      run<OP_CVT_F32_F64>(out, groups, e0, e1, &r[OP_CVT_F32_F64]) ||
-      run<OP_CVT_F32_U32>(out, groups, e0, e1, &r[OP_CVT_F32_U32]) ||
-      run<OP_PAIR_FMA_SIN>(out, groups, e0, e1, &r[OP_PAIR_FMA_SIN]) ||
-      run<OP_PAIR_FMA_MAD64>(out, groups, e0, e1, &r[OP_PAIR_FMA_MAD64]))
-    return 1;
-  std::printf("CUs %d, 8 waves/SIMD, %d chains x %d iterations per lane\n", cus, kChains,
-              kIters);
-  std::printf("%-34s %6s %14s %18s\n", "operation", "insts", "Gsteps/s",
-              "slots per step");
-  for (int op = 0; op < OP_COUNT; ++op)
-    std::printf("%-34s %6d %14.1f %18.2f\n", kNames[op], kInstPerStep[op], r[op] * 1e-9,
-                r[OP_FMA_F32] / r[op]);
-  std::printf("v_fma_f32 rate = %.2f Tlane-op/s (clock-equivalent %.3f GHz at 64 lanes/CU)\n",
-              r[OP_FMA_F32] * 1e-12, r[OP_FMA_F32] / (64.0 * cus) * 1e-9);
+  const int n = (int)(sizeof(g_entries) / sizeof(g_entries[0]));
+  for (int i = 0; i < n; ++i)
+    if (measure(g_entries[i], out, groups, e0, e1)) return 1;
+  const double fma_rate = g_entries[0].rate;
+  std::printf("gfx950 VALU issue rates: %d CUs, 8 waves/SIMD, %d chains x %d steps per lane\n",
+              cus, kChains, kIters);
+  std::printf("%-20s %6s %16s %22s\n", "chain step", "insts", "T steps/s",
+              "v_fma_f32 slots/step");
+  for (int i = 0; i < n; ++i)
+    std::printf("%-20s %6d %16.2f %22.2f\n", g_entries[i].name, g_entries[i].insts,
+                g_entries[i].rate * 1e-12, fma_rate / g_entries[i].rate);
+  std::printf("v_fma_f32: %.2f T lane-op/s = %.1f lane-ops per CU per ns\n", fma_rate * 1e-12,
+              fma_rate / cus * 1e-9);
   CHECK(hipFree(out));
   return 0;
 }
