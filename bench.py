@@ -40,6 +40,25 @@ OPS_FP32C = (10 * (2 * MAD64_COST + 4) + 4 * 2 + 2 * (4 * TRANS_COST + 3)
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock
 
 
+def counter_traffic(slots: int):
+    """HBM bytes per launch of the FP32C slice kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel sources
+    (or the launch shape) differ from those the counters were taken on."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "slice_kernel_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for src in rec["kernel_sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != rec["kernel_sources_sha256"] or int(rec["slots"]) != slots:
+            return None
+        return float(rec["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,7 +206,10 @@ def main():
     achieved = st["replica_steps"] * OPS_FP32C / kernel_s if kernel_s > 0 else 0.0
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
             "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS,
-            "traffic": None, "kernel": "slice_kernel<fp32c, underdamped>",
+            "traffic": counter_traffic(
+                torch.cuda.get_device_properties(0).multi_processor_count * 4 * 64
+                * st["tuning"]["waves_per_simd"] * st["tuning"]["replicas_per_lane"]),
+            "kernel": "slice_kernel<fp32c, underdamped>",
             "ops_per_replica_step": OPS_FP32C,
             "avg_launch_ms": st["kernel_ms"] / launches, "launches": st["n_launches"]}
 
