@@ -27,17 +27,19 @@ if ROOT not in sys.path:
 
 METRIC = "replica-steps/s FP32-comp vs FP64 at KS-pass accuracy; p50/p99 job latency"
 
-# Algorithmic VALU work per replica-step, in full-rate issue slots (a
-# quarter-rate instruction counts 4).  Per 4-step block: Philox4x32-10 with a
-# wave-uniform key = 10 rounds x (2 v_mad_u64_u32 + 4 v_xor) ; 4 uniforms
-# (cvt + fma); 2 Box-Muller pairs (log, sqrt, sin, cos + 3 mul); per step:
-# sin(phi) (scale + v_sin), gamma_k (f64 fma + cvt), Kahan phase (fma, add,
-# 2 sub), velocity (mul, fma, sub, fma), threshold compare.
-TRANS_COST = 4      # v_sin/v_cos/v_log/v_sqrt_f32 issue cost (full-rate slots)
-MAD64_COST = 4      # v_mad_u64_u32 issue cost
-OPS_FP32C = (10 * (2 * MAD64_COST + 4) + 4 * 2 + 2 * (4 * TRANS_COST + 3)
-             + 4 * ((1 + TRANS_COST) + 2 + 4 + 4 + 1)) / 4.0
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock
+# Algorithmic VALU lane-operations per replica-step of the FP32C path: the
+# method's minimal instruction mix per 4-step block, one lane-op per
+# instruction (sin and generator operations included):
+#   Philox4x32-10: 10 rounds x (2 32x32->64 products + 2 three-input XORs) = 40
+#   4 uniforms (convert + scale)                                            =  8
+#   Box-Muller: 2 x (log, sqrt, cos, sin) + 2 noise scalings                = 10
+#   bias: 1 FP64 fma + 1 convert per block + 3 FP32 increments              =  5
+#   4 steps x (sin, 4 Kahan, 3 velocity fma, threshold compare)             = 36
+#   block counter (FP64 step count, 64-bit block index)                     =  2
+OPS_FP32C = (40 + 8 + 10 + 5 + 36 + 2) / 4.0
+# MI355X FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-operations/s
+# (256 CUs x 128 FP32 lanes per clock x 2.4 GHz)
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
 
 
 def counter_traffic(slots: int):
@@ -73,6 +75,13 @@ def parse():
                     help="replicas of the oracle CPU-baseline sample (0: skip)")
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle processes (0: min(16, host cores))")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="arrival window of the serving leg (0: skip)")
+    ap.add_argument("--serve-drain", type=float, default=60.0,
+                    help="longest wait for admitted jobs after the window")
+    ap.add_argument("--serve-rho", type=float, default=0.7,
+                    help="offered load of the rate-scaled trace, as a fraction of the "
+                         "measured FP32C throughput")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scale for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -124,6 +133,67 @@ def cpu_baseline(n_rep: int, procs: int):
             "sample": f"switching-current workload, replicas 0..{n_rep - 1} (seed 2) in "
                       f"{procs} single-threaded oracle processes, {total} replica-steps, "
                       f"{wall:.1f} s wall; host CPU: {cpu}"}
+
+
+def serving_leg(capacity: float, window_s: float, drain_s: float, rho: float):
+    """Continuous batching: the serving trace (Poisson arrivals at 50 jobs/s,
+    ramp jobs with 2^10..2^18 replicas) offered at `rho` of the measured
+    capacity by stretching its arrival times; jobs arriving in `window_s` are
+    submitted to an fpt server and polled until done (at most `drain_s` more).
+    Latency is submit-to-result."""
+    import numpy as np
+    import torch
+
+    from paper_1802_05065_amd import _lib, workloads
+
+    trace = workloads.serving_trace(rate_per_s=50.0, duration_s=60.0, seed=5)
+    # work of a job, bounded by the steps to gamma = 1 (hist_k_max)
+    work = np.array([j["params"]["n_replicas"] * j["params"]["hist_k_max"] for j in trace],
+                    dtype=np.float64)
+    mean_work = float(work.mean())
+    lam = rho * capacity / mean_work
+    stretch = 50.0 / lam
+    pool_bytes = 1 << 30
+    pool = torch.empty(pool_bytes + 256, dtype=torch.uint8, device="cuda")
+    base = pool.data_ptr() + (-pool.data_ptr()) % 256
+    stream = torch.cuda.Stream()
+    srv = _lib.fpt_server_create(base, pool_bytes, "fp32c", 0, None, stream.cuda_stream)
+    pending, lat = {}, []
+    i = 0
+    t0 = time.perf_counter()
+    try:
+        while True:
+            now = time.perf_counter() - t0
+            while i < len(trace) and trace[i]["t"] * stretch <= min(now, window_s):
+                pending[_lib.fpt_submit(srv, trace[i]["params"])] = trace[i]["params"]
+                i += 1
+            for jid in list(pending):
+                r = _lib.fpt_poll(srv, jid, pending[jid]["n_bins"])
+                if r is not None:
+                    lat.append(r[2])
+                    del pending[jid]
+            arrivals_done = i >= len(trace) or trace[i]["t"] * stretch > window_s
+            if (now >= window_s and arrivals_done and not pending) or now > window_s + drain_s:
+                break
+            time.sleep(0.002)
+        elapsed = time.perf_counter() - t0
+        st = _lib.fpt_server_stats_get(srv)
+    finally:
+        _lib.fpt_server_destroy(srv)
+    lat = np.array(lat)
+    return {
+        "trace": "serving mix (Poisson, 2^10..2^18 replicas, ramp jobs) offered at "
+                 f"rho={rho} of the measured FP32C capacity",
+        "offered_jobs_per_s": lam, "window_s": window_s, "submitted": i,
+        "finished": int(lat.size), "unfinished": len(pending),
+        "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
+        "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
+        "replica_steps_per_s": st["replica_steps"] / elapsed, "launches": st["n_launches"],
+        "literal_trace": {"jobs_per_s": 50.0, "offered_replica_steps_per_s": 50.0 * mean_work,
+                          "rho": 50.0 * mean_work / capacity,
+                          "note": "the literal trace offers more work than one GPU can "
+                                  "integrate, so its queue grows without bound"},
+    }
 
 
 def main():
@@ -213,6 +283,12 @@ def main():
             "ops_per_replica_step": OPS_FP32C,
             "avg_launch_ms": st["kernel_ms"] / launches, "launches": st["n_launches"]}
 
+    latency = None
+    if args.serve_seconds > 0:
+        latency = serving_leg(value, args.serve_seconds, args.serve_drain, args.serve_rho)
+        print(f"[bench] serving: {latency['finished']} jobs, p50 {latency['p50_s']} s, "
+              f"p99 {latency['p99_s']} s", file=sys.stderr, flush=True)
+
     cpu = None
     if args.cpu_replicas > 0:
         procs = args.cpu_procs or min(16, os.cpu_count() or 1)
@@ -231,7 +307,7 @@ def main():
                  "speedup_fp32c_over_fp64": value / value64 if value64 > 0 else None,
                  "tuning": r64.stats["tuning"]},
         "ks": ks_info,
-        "latency": None,
+        "latency": latency,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
