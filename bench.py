@@ -82,6 +82,12 @@ def parse():
     ap.add_argument("--serve-rho", type=float, default=0.7,
                     help="offered load of the rate-scaled trace, as a fraction of the "
                          "measured FP32C throughput")
+    ap.add_argument("--mode", choices=("switching", "uneven", "batched"), default="switching",
+                    help="switching: the benchmark line (default); uneven: refill vs "
+                         "one-replica-per-lane on the uneven overdamped workload; batched: "
+                         "the 256-set workload in one graph-replayed persistent launch")
+    ap.add_argument("--ramp-scale", type=float, default=1.0,
+                    help="batched mode: multiply every ramp (shorter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scale for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -196,6 +202,86 @@ def serving_leg(capacity: float, window_s: float, drain_s: float, rho: float):
     }
 
 
+def uneven_mode(args):
+    """Refill vs one replica per lane on the uneven overdamped workload
+    (exponential-tailed escape times), with Appendix A's prediction."""
+    import numpy as np
+    import torch
+
+    import oracle.appendix_a as appendix_a
+    from paper_1802_05065_amd import api, workloads
+
+    p = workloads.uneven_overdamped(n_replicas=args.replicas if args.replicas != 2 ** 20
+                                    else 2 ** 22, seed=3)
+    out = {"workload": "uneven overdamped: gamma 0.8, T 0.05, dt 0.01, threshold phi0 + 2 pi",
+           "replicas": p["n_replicas"], "precision": "fp32c"}
+    steps = None
+    for sched in ("refill", "one_per_lane"):
+        tun = dict(schedule=0 if sched == "refill" else 1)
+        api.simulate(dict(p, n_replicas=min(p["n_replicas"], 2 ** 16), seed=77), "fp32c", tun,
+                     record_steps=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = api.simulate(p, "fp32c", tun)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = r.stats
+        util = st["replica_steps"] / st["lane_steps"] if st["lane_steps"] else None
+        out[sched] = {"replica_steps_per_s": st["replica_steps"] / (t1 - t0),
+                      "wall_s": t1 - t0, "lane_utilization": util,
+                      "launches": st["n_launches"], "tuning": st["tuning"]}
+        if steps is None:
+            steps = r.steps[0].cpu().numpy()
+        else:
+            assert np.array_equal(steps, r.steps[0].cpu().numpy()), "schedules disagree"
+    lanes = 64 * out["one_per_lane"]["tuning"]["replicas_per_lane"]
+    k = steps[steps > 0].astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(0))
+    emp = k.mean() / rng.choice(k, size=(20000, lanes)).max(axis=1).mean()
+    out["appendix_a"] = {
+        "threads": lanes,
+        "exponential_model_efficiency": appendix_a.efficiency(lanes, 1),
+        "empirical_escape_law_efficiency": float(emp),
+        "note": "one replica per lane: a wavefront's slots wait for its slowest replica; "
+                "Appendix A models escape times as unit exponentials (efficiency 1/H_N)"}
+    out["identical_results_across_schedules"] = True
+    print(json.dumps(out), flush=True)
+
+
+def batched_mode(args):
+    """The 256-set workload in one plan: persistent refill over all sets,
+    launches replayed through a captured hipGraph."""
+    import torch
+
+    from paper_1802_05065_amd import api, workloads
+
+    sets = workloads.batched_sets(n_sets=256, seed=4, ramp_scale=args.ramp_scale)
+    res = {}
+    for graph in (1, 0):
+        tun = dict(use_graph=graph)
+        api.simulate(workloads.batched_sets(n_sets=256, seed=4, ramp_scale=1000.0), "fp32c",
+                     tun, record_steps=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = api.simulate(sets, "fp32c", tun, record_steps=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = r.stats
+        res["graph" if graph else "stream"] = {
+            "replica_steps_per_s": st["replica_steps"] / (t1 - t0), "wall_s": t1 - t0,
+            "replica_steps": st["replica_steps"], "launches": st["n_launches"],
+            "lane_utilization": st["replica_steps"] / max(st["lane_steps"], 1),
+            "tuning": st["tuning"],
+            "censored": int(sum(m["n_censored"] for m in r.moments))}
+        if graph:
+            hist_graph = [c.tolist() for c in r.counts]
+        else:
+            assert hist_graph == [c.tolist() for c in r.counts], "graph and stream disagree"
+    print(json.dumps({"workload": "batched: 256 ramp sets", "ramp_scale": args.ramp_scale,
+                      "replicas": sum(s["n_replicas"] for s in sets), "precision": "fp32c",
+                      **res}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -204,6 +290,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.mode == "uneven":
+        uneven_mode(args)
+        return
+    if args.mode == "batched":
+        batched_mode(args)
         return
     import numpy as np
     import torch
