@@ -69,6 +69,13 @@ typedef enum {
 
 typedef enum { FPT_UNDERDAMPED = 0, FPT_OVERDAMPED = 1 } fpt_model;
 
+/* FPT_EXPLICIT: Algorithm 1's update, both phi and v from step k-1 values
+ * (small oscillations grow by 1 - h alpha + h^2 per step: unstable when
+ * dt cos(phi*) > alpha).  FPT_SEMI_IMPLICIT: v_k first, then
+ * phi_k = phi_{k-1} + dt v_k (symplectic Euler, per-step factor 1 - h alpha;
+ * same cost).  Underdamped model only. */
+typedef enum { FPT_EXPLICIT = 0, FPT_SEMI_IMPLICIT = 1 } fpt_scheme;
+
 /* FPT_FP64: every replica operation in FP64 (the plain path).
  * FPT_FP32C: replica state in FP32 with Kahan-compensated phase accumulation;
  * FP64 is kept for gamma_k from the exact integer step and for the threshold
@@ -87,6 +94,8 @@ typedef enum { FPT_SCHED_REFILL = 0, FPT_SCHED_ONE_PER_LANE = 1 } fpt_schedule;
 typedef struct fpt_params {
   int32_t model;        /* fpt_model */
   int32_t n_bins;       /* histogram bins, 1..FPT_MAX_BINS */
+  int32_t scheme;       /* fpt_scheme (underdamped only; 0 for overdamped) */
+  int32_t reserved;     /* 0 */
   double alpha;         /* damping (underdamped), >= 0 */
   double T;             /* temperature, >= 0 (T = 0: noise-free) */
   double V0;            /* potential amplitude (1 in plasma units) */

@@ -136,7 +136,8 @@ static void euler_step(const oracle_params* p, run_state* s, int64_t k,
     const double force =
         -p->alpha * s->v - p->V0 * sin(s->phi) + p->V0 * gamma_k;
     const double v_new = s->v + p->dt * force + s->sigma * r;
-    s->phi = phi_new;
+    /* explicit: phi moves with v_{k-1}; semi-implicit: with v_k */
+    s->phi = p->scheme == 1 ? s->phi + p->dt * v_new : phi_new;
     s->v = v_new;
   } else {
     const double drift = -p->V0 * sin(s->phi) + gamma_k;

@@ -11,6 +11,8 @@
  * Conventions (all readings of the paper are listed in the design notes):
  *   - model 0 = underdamped Josephson junction, the Euler update of
  *     Algorithm 1 (EscapeTime) and Algorithm 3 (SwitchingCurrent), Sect. III.B;
+ *     scheme 1 replaces it by the semi-implicit (symplectic) Euler variant,
+ *     v first and then phi with the new v (an extension, not in the paper);
  *     model 1 = overdamped washboard, the first-order analogue mentioned in
  *     Sect. II.B (the paper prints no algorithm for it).
  *   - noise amplitude D = alpha*T (Eq. (9): D = beta*theta with beta -> alpha,
@@ -33,7 +35,7 @@ extern "C" {
 
 typedef struct {
   int32_t model;       /* 0 underdamped, 1 overdamped */
-  int32_t reserved;
+  int32_t scheme;      /* underdamped: 0 explicit (Algorithm 1), 1 semi-implicit */
   double alpha;        /* damping (beta of Eq. (10)) */
   double T;            /* temperature (theta of Eq. (9)) */
   double V0;           /* potential amplitude of Eq. (10) */

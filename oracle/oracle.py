@@ -41,7 +41,7 @@ def build(force: bool = True) -> None:
 class _CParams(ctypes.Structure):
     _fields_ = [
         ("model", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
         ("alpha", ctypes.c_double),
         ("T", ctypes.c_double),
         ("V0", ctypes.c_double),
@@ -87,10 +87,11 @@ class OracleParams:
     threshold: float = math.nan
     max_steps: int = 100000
     seed: int = 1
+    scheme: int = 0
 
     def _c(self) -> _CParams:
         return _CParams(
-            int(self.model), 0, float(self.alpha), float(self.T), float(self.V0),
+            int(self.model), int(self.scheme), float(self.alpha), float(self.T), float(self.V0),
             float(self.gamma0), float(self.ramp), float(self.dt), float(self.phi0),
             float(self.v0), float(self.threshold), int(self.max_steps),
             int(self.seed) & 0xFFFFFFFFFFFFFFFF,

@@ -27,6 +27,8 @@ FPT_E_STATE = -6
 
 FPT_UNDERDAMPED = 0
 FPT_OVERDAMPED = 1
+FPT_EXPLICIT = 0
+FPT_SEMI_IMPLICIT = 1
 FPT_FP64 = 0
 FPT_FP32C = 1
 FPT_SCHED_REFILL = 0
@@ -53,6 +55,8 @@ class FptParams(ctypes.Structure):
     _fields_ = [
         ("model", ctypes.c_int32),
         ("n_bins", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("alpha", ctypes.c_double),
         ("T", ctypes.c_double),
         ("V0", ctypes.c_double),
@@ -180,7 +184,8 @@ def check(status: int, allow=(FPT_OK,)) -> int:
 def make_params(p: Dict) -> FptParams:
     """fpt_params from a dict with the field names of include/fpt.h."""
     return FptParams(
-        int(p["model"]), int(p["n_bins"]), float(p["alpha"]), float(p["T"]),
+        int(p["model"]), int(p["n_bins"]), int(p.get("scheme", 0)), 0,
+        float(p["alpha"]), float(p["T"]),
         float(p.get("V0", 1.0)), float(p["gamma0"]), float(p["ramp"]), float(p["dt"]),
         float(p["phi0"]), float(p["v0"]), float(p["threshold"]), int(p["max_steps"]),
         int(p["n_replicas"]), int(p.get("hist_k_max", 0)), int(p["seed"]) & (2**64 - 1),

@@ -154,6 +154,17 @@ __device__ __forceinline__ void step_f64_under(const ParF64& p, double kd,
   phi = phi_new;
 }
 
+// FP64 underdamped, semi-implicit (symplectic) Euler: v_k as above, then
+// phi_k = phi + dt v_k.
+__device__ __forceinline__ void step_f64_under_si(const ParF64& p, double kd,
+                                                  double r, double& phi,
+                                                  double& v) {
+  const double gamma_k = p.gamma0 + p.dgamma * kd;
+  const double force = -p.alpha * v - p.V0 * sin(phi) + p.V0 * gamma_k;
+  v = v + p.dt * force + p.sigma * r;
+  phi = phi + p.dt * v;
+}
+
 // FP64 overdamped: phi_k = phi + dt (-V0 sin phi + gamma_k) + sigma r.
 __device__ __forceinline__ void step_f64_over(const ParF64& p, double kd,
                                               double r, double& phi) {
@@ -176,6 +187,20 @@ __device__ __forceinline__ void step_f32_under(const ParF32& p, float g, float z
   phr = t;
   const float inc = __builtin_fmaf(-p.kS, s, __builtin_fmaf(zs, trig, g));
   v = __builtin_fmaf(p.damp, v, inc);
+}
+
+// FP32C underdamped, semi-implicit: the velocity first, then the phase moves
+// with the new velocity.
+__device__ __forceinline__ void step_f32_under_si(const ParF32& p, float g, float zs,
+                                                  float trig, float& phr, float& c,
+                                                  float& v) {
+  const float s = __builtin_amdgcn_sinf(phr);
+  const float inc = __builtin_fmaf(-p.kS, s, __builtin_fmaf(zs, trig, g));
+  v = __builtin_fmaf(p.damp, v, inc);
+  const float y = __builtin_fmaf(p.h_rev, v, -c);
+  const float t = phr + y;
+  c = (t - phr) - y;
+  phr = t;
 }
 
 // FP32C overdamped: the increment G_k - kS sin(2 pi phr) + sig z_k is added

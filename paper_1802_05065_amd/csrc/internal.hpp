@@ -20,6 +20,17 @@ constexpr uint32_t kInactive = 0xFFFFFFFFu;
 constexpr int kChunk = 64;         // replicas per work-queue chunk
 constexpr int kBinBits = 12;       // FPT_MAX_BINS = 1 << kBinBits
 
+// Integrator kinds (the kernel's MODEL template argument): the two models of
+// fpt_model, plus the underdamped model with the semi-implicit scheme.
+constexpr int kUnderExplicit = FPT_UNDERDAMPED;
+constexpr int kOver = FPT_OVERDAMPED;
+constexpr int kUnderSemiImplicit = 2;
+
+inline int integrator_kind(const fpt_params& p) {
+  if (p.model == FPT_OVERDAMPED) return kOver;
+  return p.scheme == FPT_SEMI_IMPLICIT ? kUnderSemiImplicit : kUnderExplicit;
+}
+
 // Per-set constants, derived on the host (Algorithm 1 / 3 preamble).
 struct alignas(16) SetDev {
   double gamma0, dgamma, dt, alpha, V0, sigma, th, phi0, v0;
@@ -35,7 +46,7 @@ struct alignas(16) SetDev {
   int64_t* out_steps;   // device, may be null
   uint64_t hist_off;    // first bin of this set in the histogram array
   uint32_t n_bins;
-  uint32_t model;
+  uint32_t model;       // integrator kind
 };
 
 // A run of at most kChunk consecutive replicas of one set.

@@ -52,7 +52,15 @@ constexpr int kThreads = 256;
   X(fma_f32_mulhi, "v_fma_f32 %[x], %[x], %[p], %[q]\n v_mul_hi_u32 %[y], %[y], %[p]", 2) \
   X(fma_f32_fma_f64, "v_fma_f64 %[d], %[d], %[a], %[b]\n v_fma_f32 %[x], %[x], %[p], %[q]", 2) \
   X(fma_f32_mad64, "v_mad_u64_u32 %[d], vcc, %[y], %[p], %[d]\n v_fma_f32 %[x], %[x], %[p], %[q]", 2) \
-  X(sin_mad64, "v_mad_u64_u32 %[d], vcc, %[y], %[p], %[d]\n v_sin_f32 %[x], %[x]", 2)
+  X(sin_mad64, "v_mad_u64_u32 %[d], vcc, %[y], %[p], %[d]\n v_sin_f32 %[x], %[x]", 2)      \
+  X(fma_f32_s, "v_fma_f32 %[x], %[x], %[ps], %[q]", 1)                                \
+  X(fma_f32_ss, "v_fma_f32 %[x], %[x], %[ps], %[ps]", 1)                              \
+  X(fmac_f32_s, "v_fmac_f32 %[x], %[ps], %[y]", 1)                                    \
+  X(fmac_f32_v, "v_fmac_f32 %[x], %[q], %[y]", 1)                                     \
+  X(fmamk_f32, "v_fmamk_f32 %[x], %[x], 0x3f7fbe77, %[q]", 1)                         \
+  X(mad_u64_u32_s0, "v_mad_u64_u32 %[d], vcc, %[x], %[ps], 0", 1)                     \
+  X(bitop3_b32_s, "v_bitop3_b32 %[x], %[x], %[y], %[ps] bitop3:0x96", 1)               \
+  X(sub_f32, "v_sub_f32 %[x], %[x], %[y]", 1)
 
 #define DECL(name, text, n)                                                           \
   __global__ __launch_bounds__(kThreads) void k_##name(float* out, float seed) {     \
@@ -69,7 +77,8 @@ constexpr int kThreads = 256;
     for (int i = 0; i < kIters; ++i) {                                                \
       _Pragma("unroll") for (int c = 0; c < kChains; ++c)                             \
         asm volatile(text : [x] "+v"(x[c]), [y] "+v"(y[c]), [d] "+v"(d[c])            \
-                     : [a] "v"(a), [b] "v"(b), [p] "v"(p), [q] "v"(q) : "vcc");       \
+                     : [a] "v"(a), [b] "v"(b), [p] "v"(p), [q] "v"(q), [ps] "s"(p)     \
+                     : "vcc");                                                        \
     }                                                                                 \
     float acc = 0.f;                                                                  \
     for (int c = 0; c < kChains; ++c) acc += x[c] + y[c] + (float)d[c];               \

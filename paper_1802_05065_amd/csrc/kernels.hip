@@ -406,8 +406,10 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const double kd = sl.kd + (double)(q + 1);
-          if constexpr (MODEL == FPT_UNDERDAMPED) {
+          if constexpr (MODEL == kUnderExplicit) {
             step_f64_under(p, kd, z[q], sl.phi, sl.v);
+          } else if constexpr (MODEL == kUnderSemiImplicit) {
+            step_f64_under_si(p, kd, z[q], sl.phi, sl.v);
           } else {
             step_f64_over(p, kd, z[q], sl.phi);
           }
@@ -441,8 +443,10 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
           const auto& p = MULTI ? sl.p : uni.p;
           const float g = q == 0 ? g0[r] : __builtin_fmaf(p.dG, (float)q, g0[r]);
           const float trig = (q & 1) ? bm[r].s[q >> 1] : bm[r].c[q >> 1];
-          if constexpr (MODEL == FPT_UNDERDAMPED) {
+          if constexpr (MODEL == kUnderExplicit) {
             step_f32_under(p, g, zs[r][q >> 1], trig, sl.phi, sl.c, sl.v);
+          } else if constexpr (MODEL == kUnderSemiImplicit) {
+            step_f32_under_si(p, g, zs[r][q >> 1], trig, sl.phi, sl.c, sl.v);
           } else {
             step_f32_over(p, g, zs[r][q >> 1], trig, sl.phi, sl.c);
           }
@@ -611,8 +615,10 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
       normals_f64(w, z);
       for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
         const double kd = s.kd + (double)(q + 1);
-        if constexpr (MODEL == FPT_UNDERDAMPED) {
+        if constexpr (MODEL == kUnderExplicit) {
           step_f64_under(s.p, kd, z[q], s.phi, s.v);
+        } else if constexpr (MODEL == kUnderSemiImplicit) {
+          step_f64_under_si(s.p, kd, z[q], s.phi, s.v);
         } else {
           step_f64_over(s.p, kd, z[q], s.phi);
         }
@@ -626,8 +632,10 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
         const float g = q == 0 ? g0 : __builtin_fmaf(s.p.dG, (float)q, g0);
         const float zs = s.p.sig * bm.radius[q >> 1];
         const float trig = (q & 1) ? bm.s[q >> 1] : bm.c[q >> 1];
-        if constexpr (MODEL == FPT_UNDERDAMPED) {
+        if constexpr (MODEL == kUnderExplicit) {
           step_f32_under(s.p, g, zs, trig, s.phi, s.c, s.v);
+        } else if constexpr (MODEL == kUnderSemiImplicit) {
+          step_f32_under_si(s.p, g, zs, trig, s.phi, s.c, s.v);
         } else {
           step_f32_over(s.p, g, zs, trig, s.phi, s.c);
         }
@@ -665,16 +673,23 @@ static hipError_t launch_slice_r(int R, bool multi, const SliceArgs& a,
                 : launch_slice_m<FP64, MODEL, 1>(multi, a, n_groups, st);
 }
 
-hipError_t launch_slice(bool fp64, int model, int R, bool multi,
-                        const SliceArgs& a, uint32_t n_groups, hipStream_t st) {
-  if (fp64) {
-    return model == FPT_OVERDAMPED
-               ? launch_slice_r<true, FPT_OVERDAMPED>(R, multi, a, n_groups, st)
-               : launch_slice_r<true, FPT_UNDERDAMPED>(R, multi, a, n_groups, st);
+template <bool FP64>
+static hipError_t launch_slice_k(int kind, int R, bool multi, const SliceArgs& a,
+                                 uint32_t n_groups, hipStream_t st) {
+  switch (kind) {
+    case kOver:
+      return launch_slice_r<FP64, kOver>(R, multi, a, n_groups, st);
+    case kUnderSemiImplicit:
+      return launch_slice_r<FP64, kUnderSemiImplicit>(R, multi, a, n_groups, st);
+    default:
+      return launch_slice_r<FP64, kUnderExplicit>(R, multi, a, n_groups, st);
   }
-  return model == FPT_OVERDAMPED
-             ? launch_slice_r<false, FPT_OVERDAMPED>(R, multi, a, n_groups, st)
-             : launch_slice_r<false, FPT_UNDERDAMPED>(R, multi, a, n_groups, st);
+}
+
+hipError_t launch_slice(bool fp64, int kind, int R, bool multi,
+                        const SliceArgs& a, uint32_t n_groups, hipStream_t st) {
+  return fp64 ? launch_slice_k<true>(kind, R, multi, a, n_groups, st)
+              : launch_slice_k<false>(kind, R, multi, a, n_groups, st);
 }
 
 hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,
@@ -725,24 +740,33 @@ hipError_t launch_normals(bool fp64, uint64_t seed, uint64_t replica0,
   return hipGetLastError();
 }
 
-hipError_t launch_trajectory(bool fp64, int model, const SetDev& sd,
+template <bool FP64>
+static void launch_trajectory_t(int kind, const SetDev& sd, uint64_t replica,
+                                int64_t n_steps, double* out_phi, double* out_v,
+                                hipStream_t st) {
+  switch (kind) {
+    case kOver:
+      hipLaunchKernelGGL((trajectory_kernel<FP64, kOver>), dim3(1), dim3(64), 0, st, sd,
+                         replica, n_steps, out_phi, out_v);
+      break;
+    case kUnderSemiImplicit:
+      hipLaunchKernelGGL((trajectory_kernel<FP64, kUnderSemiImplicit>), dim3(1), dim3(64), 0,
+                         st, sd, replica, n_steps, out_phi, out_v);
+      break;
+    default:
+      hipLaunchKernelGGL((trajectory_kernel<FP64, kUnderExplicit>), dim3(1), dim3(64), 0, st,
+                         sd, replica, n_steps, out_phi, out_v);
+  }
+}
+
+hipError_t launch_trajectory(bool fp64, int kind, const SetDev& sd,
                              uint64_t replica, int64_t n_steps, double* out_phi,
                              double* out_v, hipStream_t st) {
   if (n_steps <= 0) return hipSuccess;
   if (fp64) {
-    if (model == FPT_OVERDAMPED)
-      hipLaunchKernelGGL((trajectory_kernel<true, FPT_OVERDAMPED>), dim3(1), dim3(64),
-                         0, st, sd, replica, n_steps, out_phi, out_v);
-    else
-      hipLaunchKernelGGL((trajectory_kernel<true, FPT_UNDERDAMPED>), dim3(1), dim3(64),
-                         0, st, sd, replica, n_steps, out_phi, out_v);
+    launch_trajectory_t<true>(kind, sd, replica, n_steps, out_phi, out_v, st);
   } else {
-    if (model == FPT_OVERDAMPED)
-      hipLaunchKernelGGL((trajectory_kernel<false, FPT_OVERDAMPED>), dim3(1), dim3(64),
-                         0, st, sd, replica, n_steps, out_phi, out_v);
-    else
-      hipLaunchKernelGGL((trajectory_kernel<false, FPT_UNDERDAMPED>), dim3(1), dim3(64),
-                         0, st, sd, replica, n_steps, out_phi, out_v);
+    launch_trajectory_t<false>(kind, sd, replica, n_steps, out_phi, out_v, st);
   }
   return hipGetLastError();
 }

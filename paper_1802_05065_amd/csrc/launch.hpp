@@ -9,7 +9,8 @@
 
 namespace fpt {
 
-hipError_t launch_slice(bool fp64, int model, int R, bool multi,
+// `kind`: integrator kind (kUnderExplicit, kOver, kUnderSemiImplicit).
+hipError_t launch_slice(bool fp64, int kind, int R, bool multi,
                         const SliceArgs& a, uint32_t n_groups, hipStream_t st);
 hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,
                        uint64_t n_assign, hipStream_t st);
@@ -21,7 +22,7 @@ hipError_t launch_rng_words(uint64_t seed, uint64_t replica0, uint64_t n_rep,
 hipError_t launch_normals(bool fp64, uint64_t seed, uint64_t replica0,
                           uint64_t n_rep, uint64_t block0, uint64_t n_blk,
                           void* out, hipStream_t st);
-hipError_t launch_trajectory(bool fp64, int model, const SetDev& sd,
+hipError_t launch_trajectory(bool fp64, int kind, const SetDev& sd,
                              uint64_t replica, int64_t n_steps, double* out_phi,
                              double* out_v, hipStream_t st);
 

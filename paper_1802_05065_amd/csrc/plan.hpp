@@ -16,7 +16,7 @@ struct Plan {
   std::vector<SetDev> sets;     // derived constants, hist offsets
   std::vector<Chunk> chunks;    // multi-set work queue (64 replicas per entry)
   int precision = FPT_FP64;
-  int model = FPT_UNDERDAMPED;
+  int model = kUnderExplicit;   // integrator kind
   bool multi = false;
   fpt_tuning tuning_req{};      // as given (zeros: autotune)
   fpt_tuning tuning{};          // as used by the last simulate

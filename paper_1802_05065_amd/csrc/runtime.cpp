@@ -41,6 +41,11 @@ fpt_status validate_params(const fpt_params& p, int i) {
   if (p.model != FPT_UNDERDAMPED && p.model != FPT_OVERDAMPED)
     return fail(FPT_E_INVAL, "set %d: model %d is not 0 (underdamped) or 1 (overdamped)", i,
                 p.model);
+  if (p.scheme != FPT_EXPLICIT && p.scheme != FPT_SEMI_IMPLICIT)
+    return fail(FPT_E_INVAL, "set %d: scheme %d is not 0 (explicit) or 1 (semi-implicit)", i,
+                p.scheme);
+  if (p.model == FPT_OVERDAMPED && p.scheme != FPT_EXPLICIT)
+    return fail(FPT_E_INVAL, "set %d: the overdamped model has only scheme 0", i);
   if (p.n_bins < 1 || p.n_bins > FPT_MAX_BINS)
     return fail(FPT_E_INVAL, "set %d: n_bins %d outside [1, %d]", i, p.n_bins, FPT_MAX_BINS);
   if (!(p.dt > 0.0) || !std::isfinite(p.dt))
@@ -128,7 +133,7 @@ SetDev derive_set(const fpt_params& p) {
   s.out_steps = nullptr;
   s.hist_off = 0;
   s.n_bins = (uint32_t)p.n_bins;
-  s.model = (uint32_t)p.model;
+  s.model = (uint32_t)integrator_kind(p);
   return s;
 }
 
@@ -474,8 +479,9 @@ fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision
     return fail(FPT_E_INVAL, "precision %d is not FPT_FP64 or FPT_FP32C", precision);
   for (int32_t i = 0; i < n_sets; ++i) FPT_TRY(validate_params(params[i], i));
   for (int32_t i = 1; i < n_sets; ++i)
-    if (params[i].model != params[0].model)
-      return fail(FPT_E_INVAL, "set %d: all sets of a plan must share one model", i);
+    if (integrator_kind(params[i]) != integrator_kind(params[0]))
+      return fail(FPT_E_INVAL, "set %d: all sets of a plan must share one model and scheme",
+                  i);
   fpt_tuning t{};
   if (tuning) t = *tuning;
   if (t.schedule != FPT_SCHED_REFILL && t.schedule != FPT_SCHED_ONE_PER_LANE)
@@ -489,7 +495,7 @@ fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision
 
   Plan* p = new Plan();
   p->precision = precision;
-  p->model = params[0].model;
+  p->model = integrator_kind(params[0]);
   p->tuning_req = t;
   p->multi = n_sets > 1;
   uint64_t off = 0;
@@ -608,7 +614,7 @@ fpt_status fpt_trajectory(const fpt_params* params, uint64_t replica, int64_t n_
     return fpt::fail(FPT_E_INVAL, "precision %d unknown", precision);
   FPT_TRY(fpt::validate_params(*params, 0));
   const fpt::SetDev sd = fpt::derive_set(*params);
-  FPT_HIP(fpt::launch_trajectory(precision == FPT_FP64, params->model, sd, replica, n_steps,
+  FPT_HIP(fpt::launch_trajectory(precision == FPT_FP64, (int)sd.model, sd, replica, n_steps,
                                  out_phi, out_v, static_cast<hipStream_t>(stream)));
   return FPT_OK;
 }

@@ -415,9 +415,9 @@ fpt_status fpt_submit(fpt_server_t server, const fpt_params* params, uint64_t* j
   if (!server || !params || !job_id) return fpt::fail(FPT_E_INVAL, "NULL argument");
   fpt::Server* s = server->impl;
   FPT_TRY(fpt::validate_params(*params, 0));
-  if (params->model != s->model)
-    return fpt::fail(FPT_E_INVAL, "job model %d differs from the server's %d", params->model,
-                     s->model);
+  if (params->model != s->model || params->scheme != FPT_EXPLICIT)
+    return fpt::fail(FPT_E_INVAL, "job model %d / scheme %d: this server runs model %d with "
+                     "the explicit scheme", params->model, params->scheme, s->model);
   const uint64_t n_chunks =
       ((uint64_t)params->n_replicas + fpt::kChunk - 1) / (uint64_t)fpt::kChunk;
   std::lock_guard<std::mutex> lk(s->mu);

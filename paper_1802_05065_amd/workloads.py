@@ -25,7 +25,7 @@ def base_params(**kw) -> Dict:
     p = dict(
         model=UNDERDAMPED, alpha=0.1, T=0.02, V0=1.0, gamma0=0.0, ramp=0.0, dt=0.01,
         phi0=math.nan, v0=math.nan, threshold=math.nan, max_steps=100000, seed=1,
-        n_replicas=1024, n_bins=64, hist_k_max=0,
+        n_replicas=1024, n_bins=64, hist_k_max=0, scheme=0,
     )
     p.update(kw)
     return p
@@ -123,4 +123,6 @@ def to_oracle_kwargs(p: Dict) -> Dict:
     """The subset of fields the oracle's parameter record takes."""
     keys = ("model", "alpha", "T", "V0", "gamma0", "ramp", "dt", "phi0", "v0",
             "threshold", "max_steps", "seed")
-    return {k: p[k] for k in keys}
+    out = {k: p[k] for k in keys}
+    out["scheme"] = p.get("scheme", 0)
+    return out

@@ -63,6 +63,7 @@ def test_plan_accepts_workloads_without_gpu(lib):
     ("model", 7, "model"),
     ("alpha", -0.1, "alpha"),
     ("threshold", math.inf, "threshold"),
+    ("scheme", 2, "scheme"),
 ])
 def test_plan_rejects_bad_params(lib, field, value, needle):
     p = workloads.plain_escape()
@@ -71,6 +72,14 @@ def test_plan_rejects_bad_params(lib, field, value, needle):
         _lib.fpt_plan([p], "fp64")
     assert e.value.status == _lib.FPT_E_INVAL
     assert needle in e.value.message
+
+
+def test_overdamped_has_only_the_explicit_scheme(lib):
+    p = workloads.uneven_overdamped(n_replicas=10)
+    p["scheme"] = 1
+    with pytest.raises(_lib.FptError) as e:
+        _lib.fpt_plan([p], "fp64")
+    assert "scheme" in e.value.message
 
 
 def test_default_phi0_needs_bias_in_range(lib):

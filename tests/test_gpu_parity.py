@@ -78,6 +78,31 @@ def test_trajectory_fp64_matches_oracle(maker):
     np.testing.assert_allclose(phi[:50], rphi[:50], rtol=1e-15, atol=0)
 
 
+def test_trajectory_semi_implicit_fp64_matches_oracle():
+    p = dict(workloads.plain_escape(n_replicas=4), threshold=1e300, scheme=1)
+    phi, v = api.trajectory(p, replica=2, n_steps=4001, precision="fp64")
+    rphi, rv = oracle.trajectory(_op(p), 2, 4001)
+    np.testing.assert_allclose(phi, rphi, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(v, rv, rtol=0, atol=1e-9)
+
+
+def test_semi_implicit_escape_steps_match_oracle_and_fp32c_statistics():
+    # a set the explicit scheme integrates unstably (alpha < dt): the
+    # semi-implicit scheme keeps the replicas in the well until gamma nears 1
+    p = dict(workloads.switching_ramp(n_replicas=2048, seed=21), alpha=0.01, T=0.001,
+             ramp=1e-4, max_steps=201_000, hist_k_max=200_000, scheme=1)
+    r64 = api.simulate(p, "fp64", FIXED)
+    gpu = _steps(r64)
+    idx = np.arange(0, 2048, 128)
+    ref = np.array([oracle.escape_steps(_op(p), int(i), 1)[0] for i in idx])
+    assert np.mean(gpu[idx] == ref) >= 0.99
+    g_sw = gpu[gpu > 0] * p["ramp"] * p["dt"]
+    assert g_sw.mean() > 0.8
+    s32 = _steps(api.simulate(dict(p, seed=22), "fp32c", FIXED))
+    ks = stats.ks_2samp(s32[s32 > 0], gpu[gpu > 0])
+    assert ks.pvalue > 0.01
+
+
 def test_trajectory_fp32c_tracks_fp64():
     p = dict(workloads.switching_ramp(n_replicas=1), ramp=1e-3, threshold=1e300)
     phi32, v32 = api.trajectory(p, replica=0, n_steps=4000, precision="fp32c")

@@ -150,16 +150,20 @@ def test_inverse_gaussian_first_passage(drift_diffusion):
 # and lag-one autocorrelation 1 - h alpha.
 
 
-def test_underdamped_free_velocity_is_ar1(oracle_mod):
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_underdamped_free_velocity_is_ar1(oracle_mod, scheme):
     alpha, T, h = 0.5, 0.3, 0.05
     p = oracle_mod.OracleParams(model=0, V0=0.0, alpha=alpha, T=T, gamma0=0.0, dt=h,
-                                phi0=0.0, v0=0.0, threshold=1e300, max_steps=1, seed=3)
+                                phi0=0.0, v0=0.0, threshold=1e300, max_steps=1, seed=3,
+                                scheme=scheme)
     vs = []
     for rep in range(20):
         phi, v = oracle_mod.trajectory(p, rep, 100000)
         vs.append(v[2000:])
-        # explicit Euler: the phase moves with the velocity of the previous step
-        assert np.allclose(np.diff(phi), h * v[:-1], rtol=0, atol=1e-12)
+        # explicit Euler: the phase moves with the velocity of the previous
+        # step; semi-implicit: with the new one
+        moved = v[:-1] if scheme == 0 else v[1:]
+        assert np.allclose(np.diff(phi), h * moved, rtol=0, atol=1e-12)
     v = np.concatenate(vs)
     assert v.var() == pytest.approx(T / (1.0 - h * alpha / 2.0), rel=0.03)
     lag1 = np.mean([np.corrcoef(x[:-1], x[1:])[0, 1] for x in vs])
@@ -169,14 +173,20 @@ def test_underdamped_free_velocity_is_ar1(oracle_mod):
 # ---------------------------------------------------------------------------
 # Noise-free, small oscillation around phi = 0 (gamma = 0): the explicit Euler
 # map [[1, h], [-h, 1 - h alpha]] has determinant 1 - h alpha + h^2, so the
-# energy phi^2 + v^2 decays by that factor per step (a semi-implicit scheme
-# would give 1 - h alpha; the exact flow e^{-alpha h}).
+# energy phi^2 + v^2 decays by that factor per step; the semi-implicit map
+# [[1 - h^2, h (1 - h alpha)], [-h, 1 - h alpha]] has determinant 1 - h alpha
+# (the exact flow: e^{-alpha h}).
 
 
-def test_explicit_euler_amplification(oracle_mod):
+@pytest.mark.parametrize("scheme,factor", [
+    (0, lambda h, a: 1.0 - h * a + h * h),   # Algorithm 1: explicit
+    (1, lambda h, a: 1.0 - h * a),           # semi-implicit (symplectic) variant
+])
+def test_euler_amplification(oracle_mod, scheme, factor):
     alpha, h = 0.02, 0.01
     p = oracle_mod.OracleParams(model=0, V0=1.0, alpha=alpha, T=0.0, gamma0=0.0, dt=h,
-                                phi0=1e-4, v0=0.0, threshold=1.0, max_steps=1, seed=1)
+                                phi0=1e-4, v0=0.0, threshold=1.0, max_steps=1, seed=1,
+                                scheme=scheme)
     n = 200000
     phi, v = oracle_mod.trajectory(p, 0, n)
     E = phi**2 + v**2
@@ -184,7 +194,7 @@ def test_explicit_euler_amplification(oracle_mod):
     e0 = E[:period].mean()
     e1 = E[-period:].mean()
     rate = math.log(e1 / e0) / (n - period)
-    assert rate == pytest.approx(math.log(1.0 - h * alpha + h * h), rel=0.01)
+    assert rate == pytest.approx(math.log(factor(h, alpha)), rel=0.01)
 
 
 # ---------------------------------------------------------------------------
@@ -193,8 +203,8 @@ def test_explicit_euler_amplification(oracle_mod):
 # phi'' + alpha phi' + sin(phi) = ramp*t up to the Euler O(dt) error.
 
 
-@pytest.mark.parametrize("ramp", [1e-3, 3e-4])
-def test_deterministic_switching(oracle_mod, ramp):
+@pytest.mark.parametrize("ramp,scheme", [(1e-3, 0), (3e-4, 0), (1e-3, 1)])
+def test_deterministic_switching(oracle_mod, ramp, scheme):
     from scipy.integrate import solve_ivp
 
     alpha = 0.1
@@ -213,7 +223,7 @@ def test_deterministic_switching(oracle_mod, ramp):
     for dt in (0.01, 0.005):
         p = oracle_mod.OracleParams(model=0, alpha=alpha, T=0.0, gamma0=0.0, ramp=ramp,
                                     dt=dt, phi0=0.0, v0=0.0, threshold=2 * math.pi,
-                                    max_steps=10**9, seed=1)
+                                    max_steps=10**9, seed=1, scheme=scheme)
         k = int(oracle_mod.escape_steps(p, 0, 1)[0])
         assert k > 0
         assert ramp * dt * k > 1.0  # never before gamma reaches 1
