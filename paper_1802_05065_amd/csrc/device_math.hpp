@@ -92,7 +92,10 @@ __device__ __forceinline__ BoxMullerF32 box_muller_f32(const Words& w) {
 #pragma unroll
   for (int pair = 0; pair < 2; ++pair) {
     const float a = __builtin_fmaf((float)x[2 * pair], 0x1p-32f, 0x1p-33f);
-    const float b = (float)x[2 * pair + 1] * 0x1p-32f;
+    // angle: 1 + (x >> 9) 2^-23 in [1, 2) revolutions in one v_alignbit_b32
+    // (the 23 leading bits of x as the mantissa of a float with exponent 0);
+    // sin and cos have period 1 in revolutions
+    const float b = __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x[2 * pair + 1], 9));
     bm.radius[pair] = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(a));
     bm.c[pair] = __builtin_amdgcn_cosf(b);
     bm.s[pair] = __builtin_amdgcn_sinf(b);
@@ -216,8 +219,8 @@ __device__ __forceinline__ void step_f32_over(const ParF32& p, float g, float zs
 }
 
 // G_k of the block's first step, from the exact step count k1 = 4 j + 1.
-__device__ __forceinline__ float block_g_f32(const ParF32& p, double k1) {
-  return (float)__builtin_fma(p.gB, k1, p.gA);
+__device__ __forceinline__ float block_g_f32(double gB, double k1, double gA) {
+  return (float)__builtin_fma(gB, k1, gA);
 }
 
 // Test of the compensated phase against the FP64 threshold (revolutions):

@@ -40,7 +40,7 @@ template <>
 struct Slot<true> {
   uint32_t set;
   uint64_t idx, j;
-  double kd;  // 4 j as a double (exact below 2^53)
+  double kd;  // 4 j + 1, the step number of the block's first step (exact)
   double phi, v;
   float c;    // unused in FP64
   ParF64 p;
@@ -78,7 +78,7 @@ __device__ __forceinline__ void start_replica(Slot<FP64>& s, uint32_t set,
   s.set = set;
   s.idx = idx;
   s.j = 0;
-  s.kd = 0.0;
+  s.kd = 1.0;
   if constexpr (FP64) {
     s.phi = sd.phi0;
     s.v = sd.v0;
@@ -122,7 +122,7 @@ __device__ __forceinline__ void restore_slot(const SliceArgs& a, uint64_t slot,
   if (s.set == kInactive) return;
   s.idx = a.st_idx[slot];
   s.j = a.st_j[slot];
-  s.kd = 4.0 * (double)s.j;
+  s.kd = 4.0 * (double)s.j + 1.0;
   const unsigned long long ph = a.st_phi[slot];
   const unsigned long long vv = a.st_v[slot];
   if constexpr (FP64) {
@@ -326,6 +326,26 @@ __device__ __forceinline__ bool map_flat(const SliceArgs& a, uint64_t flat,
 // ---------------------------------------------------------------------------
 // The integrator launch.
 
+// Smallest value of x over the wavefront (rare paths only).
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, off));
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+// Blocks the active lanes of a slot can run before one of them reaches its
+// last allowed block: min over active lanes of jmax - j (saturated).
+template <bool FP64>
+__device__ __forceinline__ uint32_t blocks_to_cap(const Slot<FP64>& sl, uint64_t jmax,
+                                                  bool active) {
+  uint32_t left = 0xFFFFFFFFu;
+  if (active) {
+    const uint64_t d = jmax > sl.j ? jmax - sl.j : 0ull;
+    left = d > 0x7FFFFFFFull ? 0x7FFFFFFFu : (uint32_t)d;
+  }
+  return wave_min_u32(left);
+}
+
 template <bool FP64, int MODEL, int R, bool MULTI>
 __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
   __shared__ LdsTables tab;
@@ -342,16 +362,30 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
 
   const uint64_t lane_g = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
   const uint32_t lane = lane_id();
+  const uint64_t lane_bit = 1ull << lane;
 
   // Uniform parameters of a single-set plan (scalar registers).
   Slot<FP64> uni;
   load_params(uni, a.sets[0]);
+  double gA_uni = 0.0;
+  if constexpr (!FP64) {
+    // one vector copy, so the per-block FP64 fma reads a single scalar pair
+    gA_uni = uni.p.gA;
+    asm volatile("" : "+v"(gA_uni));
+  }
 
   Slot<FP64> s[R];
+  // activity of each slot as a wavefront mask, and the number of blocks all
+  // its active lanes can run before one reaches its step cap
+  uint64_t amask[R];
+  uint32_t safe[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     restore_slot(a, (uint64_t)r * a.n_lanes + lane_g, s[r]);
-    if (MULTI && s[r].set != kInactive) load_params(s[r], a.sets[s[r].set]);
+    const bool act = s[r].set != kInactive;
+    if (MULTI && act) load_params(s[r], a.sets[s[r].set]);
+    amask[r] = __ballot(act);
+    safe[r] = blocks_to_cap(s[r], MULTI ? s[r].jmax : uni.jmax, act);
   }
 
   bool starved = false;
@@ -361,8 +395,7 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
     if (a.refill && !starved) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const bool free_slot = s[r].set == kInactive;
-        const uint64_t need = __ballot(free_slot);
+        const uint64_t need = ~amask[r];
         if (need) {
           const uint32_t want = (uint32_t)__popcll(need);
           const int leader = __ffsll((unsigned long long)need) - 1;
@@ -372,7 +405,8 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
           got = __builtin_amdgcn_readlane((int)got, leader);
           base = read_lane_u64(base, leader);
           if (got < want) starved = true;
-          if (free_slot) {
+          bool assigned = false;
+          if (need & lane_bit) {
             const uint32_t rk = rank_in(need);
             uint32_t set;
             uint64_t idx;
@@ -380,15 +414,22 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
               const SetDev& sd = a.sets[set];
               start_replica(s[r], set, idx, sd);
               if (MULTI) load_params(s[r], sd);
+              assigned = true;
             }
+          }
+          const uint64_t newly = __ballot(assigned);
+          if (newly) {
+            amask[r] |= newly;
+            safe[r] = blocks_to_cap(s[r], MULTI ? s[r].jmax : uni.jmax,
+                                    (amask[r] & lane_bit) != 0);
           }
         }
       }
     }
-    bool any = false;
+    uint64_t any = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) any |= s[r].set != kInactive;
-    if (__ballot(any) == 0) break;
+    for (int r = 0; r < R; ++r) any |= amask[r];
+    if (any == 0) break;
     ++blocks_run;
 
     // ---- 4 Euler steps per slot
@@ -405,7 +446,7 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
         normals_f64(w, z);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const double kd = sl.kd + (double)(q + 1);
+          const double kd = sl.kd + (double)q;
           if constexpr (MODEL == kUnderExplicit) {
             step_f64_under(p, kd, z[q], sl.phi, sl.v);
           } else if constexpr (MODEL == kUnderSemiImplicit) {
@@ -429,7 +470,7 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
                                       (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32),
                                       MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
         bm[r] = box_muller_f32(w);
-        g0[r] = block_g_f32(p, sl.kd + 1.0);
+        g0[r] = block_g_f32(p.gB, sl.kd, MULTI ? p.gA : gA_uni);
         zs[r][0] = p.sig * bm[r].radius[0];
         zs[r][1] = p.sig * bm[r].radius[1];
       }
@@ -459,12 +500,12 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const auto& p = MULTI ? s[r].p : uni.p;
-        const uint64_t any_near = near[r][0] | near[r][1] | near[r][2] | near[r][3];
+        esc[r][0] = esc[r][1] = esc[r][2] = esc[r][3] = 0ull;
+        if (near[r][0] | near[r][1] | near[r][2] | near[r][3]) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          esc[r][q] = any_near ? (__ballot(above_f64(ph_q[r][q], c_q[r][q], p.th_rev)) &
-                                  near[r][q])
-                               : 0ull;
+          for (int q = 0; q < 4; ++q)
+            esc[r][q] = __ballot(above_f64(ph_q[r][q], c_q[r][q], p.th_rev)) & near[r][q];
+        }
       }
     }
 
@@ -472,21 +513,19 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       Slot<FP64>& sl = s[r];
-      const bool active = sl.set != kInactive;
       const uint64_t jmax = MULTI ? sl.jmax : uni.jmax;
-      const uint64_t act = __ballot(active);
-      const uint64_t crossed = (esc[r][0] | esc[r][1] | esc[r][2] | esc[r][3]) & act;
-      const uint64_t last = __ballot(active && sl.j >= jmax);
+      const uint64_t crossed = (esc[r][0] | esc[r][1] | esc[r][2] | esc[r][3]) & amask[r];
+      const bool check_cap = safe[r] == 0;
+      const uint64_t last = check_cap ? (__ballot(sl.j >= jmax) & amask[r]) : 0ull;
       if (crossed | last) {
         bool fin = false;
         int64_t k = -1;
-        if (active) {
-          const uint64_t bit = 1ull << lane;
+        if ((crossed | last) & lane_bit) {
           int q1 = 0;
-          if (esc[r][0] & bit) q1 = 1;
-          else if (esc[r][1] & bit) q1 = 2;
-          else if (esc[r][2] & bit) q1 = 3;
-          else if (esc[r][3] & bit) q1 = 4;
+          if (esc[r][0] & lane_bit) q1 = 1;
+          else if (esc[r][1] & lane_bit) q1 = 2;
+          else if (esc[r][2] & lane_bit) q1 = 3;
+          else if (esc[r][3] & lane_bit) q1 = 4;
           const int64_t kesc = q1 ? (int64_t)(4 * sl.j) + q1 : 0;
           const int64_t max_steps = a.sets[MULTI ? sl.set : 0].max_steps;
           if (q1 && kesc <= max_steps) {
@@ -499,9 +538,15 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
         }
         record_finished(tab, a, fin, sl.set, sl.idx, k);
         if (fin) sl.set = kInactive;
+        amask[r] &= ~__ballot(fin);
       }
       sl.j += 1;
       sl.kd += 4.0;
+      if (check_cap) {
+        safe[r] = blocks_to_cap(sl, jmax, (amask[r] & lane_bit) != 0);
+      } else {
+        --safe[r];
+      }
     }
   }
 
@@ -614,7 +659,7 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
       double z[4];
       normals_f64(w, z);
       for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
-        const double kd = s.kd + (double)(q + 1);
+        const double kd = s.kd + (double)q;
         if constexpr (MODEL == kUnderExplicit) {
           step_f64_under(s.p, kd, z[q], s.phi, s.v);
         } else if constexpr (MODEL == kUnderSemiImplicit) {
@@ -627,7 +672,7 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
       }
     } else {
       const BoxMullerF32 bm = box_muller_f32(w);
-      const float g0 = block_g_f32(s.p, s.kd + 1.0);
+      const float g0 = block_g_f32(s.p.gB, s.kd, s.p.gA);
       for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
         const float g = q == 0 ? g0 : __builtin_fmaf(s.p.dG, (float)q, g0);
         const float zs = s.p.sig * bm.radius[q >> 1];
