@@ -11,6 +11,7 @@ from .oracle import (  # noqa: F401
     derived,
     escape_steps,
     histogram,
+    mt19937,
     normals,
     philox4x32_10,
     replica_steps,

@@ -58,6 +58,52 @@ void oracle_rng_words(uint64_t seed, uint64_t replica, uint64_t block,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Algorithm 2: the Mersenne Twister MT19937 (Matsumoto and Nishimura).
+ * Initialization: mt[0] = seed, mt[i] = 1812433253 (mt[i-1] xor
+ * (mt[i-1] >> 30)) + i.  Every 624 outputs the whole state is regenerated
+ * (twist, with the 0x80000000 / 0x7fffffff split, offset 397 and the matrix
+ * 0x9908b0df); each output is tempered by the shifts 11, 7, 15, 18 with the
+ * masks 0x9d2c5680 and 0xefc60000.                                        */
+
+typedef struct {
+  uint32_t mt[624];
+  int index;
+} mt_state;
+
+static void mt_seed(mt_state* s, uint32_t seed) {
+  s->mt[0] = seed;
+  for (int i = 1; i < 624; ++i)
+    s->mt[i] = 1812433253u * (s->mt[i - 1] ^ (s->mt[i - 1] >> 30)) + (uint32_t)i;
+  s->index = 624;
+}
+
+static void mt_twist(mt_state* s) {
+  for (int i = 0; i < 624; ++i) {
+    const uint32_t y = (s->mt[i] & 0x80000000u) | (s->mt[(i + 1) % 624] & 0x7fffffffu);
+    uint32_t next = s->mt[(i + 397) % 624] ^ (y >> 1);
+    if (y & 1u) next ^= 0x9908b0dfu;
+    s->mt[i] = next;
+  }
+  s->index = 0;
+}
+
+static uint32_t mt_next(mt_state* s) {
+  if (s->index >= 624) mt_twist(s);
+  uint32_t y = s->mt[s->index++];
+  y ^= y >> 11;
+  y ^= (y << 7) & 0x9d2c5680u;
+  y ^= (y << 15) & 0xefc60000u;
+  y ^= y >> 18;
+  return y;
+}
+
+void oracle_mt19937(uint32_t seed, uint64_t n, uint32_t* out) {
+  mt_state s;
+  mt_seed(&s, seed);
+  for (uint64_t i = 0; i < n; ++i) out[i] = mt_next(&s);
+}
+
+/* ---------------------------------------------------------------------- */
 /* nrand() of Sect. III.B: Box-Muller on uniforms.  A 32-bit word x maps to
  * u = (x + 1/2) 2^-32, which lies strictly inside (0, 1) so log(u) is finite.
  * Each pair of uniforms (a, b) gives two normals
@@ -67,10 +113,7 @@ static double word_to_uniform(uint32_t x) {
   return ((double)x + 0.5) * 0x1p-32;
 }
 
-void oracle_normals(uint64_t seed, uint64_t replica, uint64_t block,
-                    double z[4]) {
-  uint32_t w[4];
-  oracle_rng_words(seed, replica, block, w);
+static void box_muller4(const uint32_t w[4], double z[4]) {
   for (int pair = 0; pair < 2; ++pair) {
     const double a = word_to_uniform(w[2 * pair]);
     const double b = word_to_uniform(w[2 * pair + 1]);
@@ -79,6 +122,37 @@ void oracle_normals(uint64_t seed, uint64_t replica, uint64_t block,
     z[2 * pair] = radius * cos(angle);
     z[2 * pair + 1] = radius * sin(angle);
   }
+}
+
+void oracle_normals(uint64_t seed, uint64_t replica, uint64_t block,
+                    double z[4]) {
+  uint32_t w[4];
+  oracle_rng_words(seed, replica, block, w);
+  box_muller4(w, z);
+}
+
+/* Source of the 4 words of each block of one replica. */
+typedef struct {
+  int rng;
+  uint64_t seed, replica;
+  mt_state mt;
+} word_source;
+
+static void source_init(word_source* src, const oracle_params* p, uint64_t replica) {
+  src->rng = p->rng;
+  src->seed = p->seed;
+  src->replica = replica;
+  if (p->rng == 1) mt_seed(&src->mt, (uint32_t)(p->seed + replica));
+}
+
+static void source_normals(word_source* src, uint64_t block, double z[4]) {
+  uint32_t w[4];
+  if (src->rng == 1) {
+    for (int i = 0; i < 4; ++i) w[i] = mt_next(&src->mt);
+  } else {
+    oracle_rng_words(src->seed, src->replica, block, w);
+  }
+  box_muller4(w, z);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -149,12 +223,14 @@ int64_t oracle_escape_step(const oracle_params* p, uint64_t replica,
                            double* phi_end, double* v_end) {
   run_state s;
   load_state(p, &s);
+  word_source src;
+  source_init(&src, p, replica);
   double z[4] = {0, 0, 0, 0};
   int64_t result = -1;
   for (int64_t k = 1; k <= p->max_steps; ++k) {
     const int64_t j = (k - 1) / 4;
     const int q = (int)((k - 1) % 4);
-    if (q == 0) oracle_normals(p->seed, replica, (uint64_t)j, z);
+    if (q == 0) source_normals(&src, (uint64_t)j, z);
     euler_step(p, &s, k, z[q]);
     if (s.phi > s.th) {
       result = k;
@@ -179,11 +255,13 @@ void oracle_trajectory(const oracle_params* p, uint64_t replica,
                        int64_t n_steps, double* phi, double* v) {
   run_state s;
   load_state(p, &s);
+  word_source src;
+  source_init(&src, p, replica);
   double z[4] = {0, 0, 0, 0};
   for (int64_t k = 1; k <= n_steps; ++k) {
     const int64_t j = (k - 1) / 4;
     const int q = (int)((k - 1) % 4);
-    if (q == 0) oracle_normals(p->seed, replica, (uint64_t)j, z);
+    if (q == 0) source_normals(&src, (uint64_t)j, z);
     euler_step(p, &s, k, z[q]);
     phi[k - 1] = s.phi;
     if (v) v[k - 1] = s.v;

@@ -22,7 +22,9 @@
  *     ramp*dt; ramp = 0 gives the fixed bias of Algorithm 1).
  *   - Gaussian draws: Box-Muller on Philox4x32-10 words keyed by
  *     (seed, replica, block), replacing the paper's Mersenne Twister
- *     (Algorithm 2) by a counter-based generator.
+ *     (Algorithm 2) by a counter-based generator; rng = 1 selects the paper's
+ *     generator instead: one MT19937 per replica seeded with seed + replica
+ *     (Sect. III.B), its words taken 4 per block in stream order.
  */
 #ifndef FPT_ORACLE_H
 #define FPT_ORACLE_H
@@ -36,6 +38,8 @@ extern "C" {
 typedef struct {
   int32_t model;       /* 0 underdamped, 1 overdamped */
   int32_t scheme;      /* underdamped: 0 explicit (Algorithm 1), 1 semi-implicit */
+  int32_t rng;         /* 0 Philox4x32-10; 1 MT19937 per replica (Algorithm 2) */
+  int32_t reserved;
   double alpha;        /* damping (beta of Eq. (10)) */
   double T;            /* temperature (theta of Eq. (9)) */
   double V0;           /* potential amplitude of Eq. (10) */
@@ -70,6 +74,10 @@ void oracle_rng_words(uint64_t seed, uint64_t replica, uint64_t block,
  * pair): z[0], z[1] from words 0,1 and z[2], z[3] from words 2,3. */
 void oracle_normals(uint64_t seed, uint64_t replica, uint64_t block,
                     double z[4]);
+
+/* MT19937 (Matsumoto, Nishimura 1998): the first n outputs of the generator
+ * seeded by the standard initialization with the 32-bit seed. */
+void oracle_mt19937(uint32_t seed, uint64_t n, uint32_t* out);
 
 /* Resolve NaN defaults and the per-step constants of the plan.
  * sigma_out, dgamma_out, phi0_out, v0_out, th_out may be NULL. */

@@ -33,6 +33,8 @@ int main(int argc, char** argv) {
   oracle_params p;
   p.model = atoi(argv[1]);
   p.scheme = 0;
+  p.rng = 0;
+  p.reserved = 0;
   p.alpha = strtod(argv[2], NULL);
   p.T = strtod(argv[3], NULL);
   p.V0 = strtod(argv[4], NULL);

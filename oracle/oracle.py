@@ -42,6 +42,8 @@ class _CParams(ctypes.Structure):
     _fields_ = [
         ("model", ctypes.c_int32),
         ("scheme", ctypes.c_int32),
+        ("rng", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("alpha", ctypes.c_double),
         ("T", ctypes.c_double),
         ("V0", ctypes.c_double),
@@ -88,10 +90,11 @@ class OracleParams:
     max_steps: int = 100000
     seed: int = 1
     scheme: int = 0
+    rng: int = 0
 
     def _c(self) -> _CParams:
         return _CParams(
-            int(self.model), int(self.scheme), float(self.alpha), float(self.T), float(self.V0),
+            int(self.model), int(self.scheme), int(self.rng), 0, float(self.alpha), float(self.T), float(self.V0),
             float(self.gamma0), float(self.ramp), float(self.dt), float(self.phi0),
             float(self.v0), float(self.threshold), int(self.max_steps),
             int(self.seed) & 0xFFFFFFFFFFFFFFFF,
@@ -124,6 +127,7 @@ def _lib() -> ctypes.CDLL:
             i64p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
             u64p, ctypes.POINTER(_CMoments),
         ]
+        lib.oracle_mt19937.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u32p]
         lib.oracle_replica_steps.argtypes = [i64p, ctypes.c_uint64, ctypes.c_int64]
         lib.oracle_replica_steps.restype = ctypes.c_uint64
         _lib_handle = lib
@@ -148,6 +152,13 @@ def rng_words(seed: int, replica: int, block: int) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     _lib().oracle_rng_words(seed & (2**64 - 1), replica, block, _ptr(out, ctypes.c_uint32))
     return out
+
+
+def mt19937(seed: int, n: int) -> np.ndarray:
+    """First n outputs of MT19937 with the standard 32-bit seeding."""
+    out = np.zeros(max(n, 1), dtype=np.uint32)
+    _lib().oracle_mt19937(seed & 0xFFFFFFFF, n, _ptr(out, ctypes.c_uint32))
+    return out[:n]
 
 
 def normals(seed: int, replica: int, block: int) -> np.ndarray:

@@ -25,7 +25,7 @@ def base_params(**kw) -> Dict:
     p = dict(
         model=UNDERDAMPED, alpha=0.1, T=0.02, V0=1.0, gamma0=0.0, ramp=0.0, dt=0.01,
         phi0=math.nan, v0=math.nan, threshold=math.nan, max_steps=100000, seed=1,
-        n_replicas=1024, n_bins=64, hist_k_max=0, scheme=0,
+        n_replicas=1024, n_bins=64, hist_k_max=0, scheme=0, rng=0,
     )
     p.update(kw)
     return p
@@ -125,4 +125,5 @@ def to_oracle_kwargs(p: Dict) -> Dict:
             "threshold", "max_steps", "seed")
     out = {k: p[k] for k in keys}
     out["scheme"] = p.get("scheme", 0)
+    out["rng"] = p.get("rng", 0)
     return out

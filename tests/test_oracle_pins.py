@@ -351,10 +351,18 @@ def _philox_py(ctr, key):
     return x
 
 
+def _mt_words(seed, n):
+    """numpy's own MT19937 (standard 32-bit seeding), independent of the oracle."""
+    bg = np.random.MT19937()
+    bg._legacy_seeding(seed & 0xFFFFFFFF)
+    return [int(x) & 0xFFFFFFFF for x in bg.random_raw(n)]
+
+
 def _brute_escape(p, replica, mp):
     mp.mp.dps = 50
     seed = p["seed"]
     key = (seed & 0xFFFFFFFF, seed >> 32)
+    mt = _mt_words(seed + replica, 4 * ((p["max_steps"] + 3) // 4)) if p.get("rng") == 1 else None
     alpha, T, V0, dt = (mp.mpf(p[k]) for k in ("alpha", "T", "V0", "dt"))
     sigma = mp.sqrt(2 * alpha * T * dt)
     phi, v, th = mp.mpf(p["phi0"]), mp.mpf(p["v0"]), mp.mpf(p["threshold"])
@@ -364,7 +372,10 @@ def _brute_escape(p, replica, mp):
     for k in range(1, p["max_steps"] + 1):
         j, q = divmod(k - 1, 4)
         if q == 0:
-            w = _philox_py([j & 0xFFFFFFFF, j >> 32, replica & 0xFFFFFFFF, replica >> 32], key)
+            if mt is not None:
+                w = mt[4 * j:4 * j + 4]
+            else:
+                w = _philox_py([j & 0xFFFFFFFF, j >> 32, replica & 0xFFFFFFFF, replica >> 32], key)
             u = [(mp.mpf(x) + mp.mpf(0.5)) / mp.mpf(2) ** 32 for x in w]
             z = []
             for a, b in ((u[0], u[1]), (u[2], u[3])):
@@ -378,11 +389,13 @@ def _brute_escape(p, replica, mp):
     return -1, near
 
 
-def test_brute_force_tiny(oracle_mod):
+@pytest.mark.parametrize("rng", [0, 1])
+def test_brute_force_tiny(oracle_mod, rng):
     mp = pytest.importorskip("mpmath")
     phi0 = math.asin(0.95)
     p = dict(model=0, alpha=0.1, T=0.02, V0=1.0, gamma0=0.95, ramp=0.0, dt=0.01,
-             phi0=phi0, v0=0.0, threshold=phi0 + 2 * math.pi, max_steps=3000, seed=1)
+             phi0=phi0, v0=0.0, threshold=phi0 + 2 * math.pi, max_steps=3000, seed=1,
+             rng=rng)
     op = oracle_mod.OracleParams(**p)
     got = oracle_mod.escape_steps(op, 0, 12)
     escaped = 0
@@ -392,6 +405,41 @@ def test_brute_force_tiny(oracle_mod):
             assert k == got[r], r
         escaped += k > 0
     assert escaped >= 1  # at least one replica exercises the escape branch
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2's generator, MT19937, against numpy's implementation and the
+# check value the C++ standard fixes for std::mt19937 ([rand.predef]: the
+# 10000th output of a default-seeded (5489) engine is 4123659995).
+
+
+@pytest.mark.parametrize("seed", [0, 1, 5489, 123456789, 2**32 - 1])
+def test_mt19937_matches_numpy(oracle_mod, seed):
+    n = 2000  # three state regenerations
+    assert oracle_mod.mt19937(seed, n).tolist() == _mt_words(seed, n)
+
+
+def test_mt19937_standard_check_value(oracle_mod):
+    assert int(oracle_mod.mt19937(5489, 10000)[-1]) == 4123659995
+
+
+def test_mt_mode_seeds_each_replica_with_seed_plus_index(oracle_mod):
+    # zero potential, no damping term in the position: the overdamped chain
+    # phi_k = phi_{k-1} + gamma dt + sqrt(2 T dt) z_k exposes the normals
+    T, dt = 0.5, 0.125
+    op = oracle_mod.OracleParams(model=1, alpha=1.0, T=T, V0=0.0, gamma0=0.0, ramp=0.0,
+                                 dt=dt, phi0=0.0, v0=0.0, threshold=1e9, max_steps=16,
+                                 seed=41, rng=1)
+    for replica in (0, 3):
+        phi, _ = oracle_mod.trajectory(op, replica, 16)
+        z = np.diff(np.concatenate([[0.0], phi])) / math.sqrt(2 * T * dt)
+        u = (np.array(_mt_words(41 + replica, 16), dtype=np.float64) + 0.5) / 2.0**32
+        for pair in range(8):
+            a, b = u[2 * pair], u[2 * pair + 1]
+            assert z[2 * pair] ** 2 + z[2 * pair + 1] ** 2 == pytest.approx(-2 * math.log(a), rel=1e-9)
+            ang = math.atan2(z[2 * pair + 1], z[2 * pair]) % (2 * math.pi)
+            d = abs(ang - 2 * math.pi * b)
+            assert min(d, 2 * math.pi - d) < 1e-7
 
 
 # ---------------------------------------------------------------------------
