@@ -82,10 +82,12 @@ def parse():
     ap.add_argument("--serve-rho", type=float, default=0.7,
                     help="offered load of the rate-scaled trace, as a fraction of the "
                          "measured FP32C throughput")
-    ap.add_argument("--mode", choices=("switching", "uneven", "batched"), default="switching",
+    ap.add_argument("--mode", choices=("switching", "uneven", "batched", "mt"),
+                    default="switching",
                     help="switching: the benchmark line (default); uneven: refill vs "
                          "one-replica-per-lane on the uneven overdamped workload; batched: "
-                         "the 256-set workload in one graph-replayed persistent launch")
+                         "the 256-set workload in one graph-replayed persistent launch; mt: "
+                         "the switching workload with per-replica MT19937 against Philox")
     ap.add_argument("--ramp-scale", type=float, default=1.0,
                     help="batched mode: multiply every ramp (shorter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -282,6 +284,61 @@ def batched_mode(args):
                       **res}), flush=True)
 
 
+# MT19937 mode: per 4-step block a lane loads two 16-byte state groups and
+# stores one (the lazily regenerated words), 12 bytes per replica-step.
+MT_BYTES_PER_REPLICA_STEP = 48 / 4.0
+PEAK_HBM = 8.0e12
+
+
+def mt_mode(args):
+    """The switching workload drawn from Algorithm 2's generator (one MT19937
+    per replica) against the same workload on Philox4x32-10, both FP32C."""
+    import numpy as np
+    import torch
+    from scipy import stats
+
+    from paper_1802_05065_amd import api, workloads
+
+    n = args.replicas if args.replicas != 2 ** 20 else 2 ** 18
+    out = {"workload": "switching-current ramp (as the benchmark line), FP32C",
+           "replicas": n}
+    samples = {}
+    for rng in ("mt19937", "philox"):
+        code = 1 if rng == "mt19937" else 0
+        api.simulate(workloads.switching_ramp(n_replicas=n, seed=99) | dict(
+            ramp=1e-3, max_steps=20_100, hist_k_max=20_000, rng=code), "fp32c",
+            record_steps=False)
+        p = workloads.switching_ramp(n_replicas=n, seed=2 if code else 3) | dict(rng=code)
+        plan = api.Plan([p], "fp32c", None, torch.device("cuda", 0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = plan.run()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = r.stats
+        kernel_s = st["kernel_ms"] * 1e-3
+        leg = {"replica_steps_per_s": st["replica_steps"] / (t1 - t0), "wall_s": t1 - t0,
+               "launches": st["n_launches"], "tuning": st["tuning"],
+               "avg_launch_ms": st["kernel_ms"] / max(st["n_launches"], 1)}
+        if code:
+            bw = st["replica_steps"] * MT_BYTES_PER_REPLICA_STEP / kernel_s
+            leg["roofline"] = {"bound": "hbm", "achieved": bw / 1e9, "peak": PEAK_HBM / 1e9,
+                               "unit": "GB/s", "frac": bw / PEAK_HBM,
+                               "bytes_per_replica_step": MT_BYTES_PER_REPLICA_STEP}
+        out[rng] = leg
+        samples[rng] = r.steps[0].cpu().numpy()
+        print(f"[bench] {rng}: {leg['replica_steps_per_s']:.4e} replica-steps/s",
+              file=sys.stderr, flush=True)
+    a, b = samples["mt19937"], samples["philox"]
+    a, b = a[a > 0], b[b > 0]
+    ks = stats.ks_2samp(a, b)
+    out["mt_over_philox"] = (out["mt19937"]["replica_steps_per_s"]
+                             / out["philox"]["replica_steps_per_s"])
+    out["ks_mt_vs_philox"] = {"pvalue": float(ks.pvalue),
+                              "mean_mt": float(a.mean()), "mean_philox": float(b.mean())}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -296,6 +353,9 @@ def main():
         return
     if args.mode == "batched":
         batched_mode(args)
+        return
+    if args.mode == "mt":
+        mt_mode(args)
         return
     import numpy as np
     import torch

@@ -82,6 +82,15 @@ typedef enum { FPT_EXPLICIT = 0, FPT_SEMI_IMPLICIT = 1 } fpt_scheme;
  * test near the threshold.  The same Philox words feed both. */
 typedef enum { FPT_FP64 = 0, FPT_FP32C = 1 } fpt_precision;
 
+/* Normal-number source.  FPT_RNG_PHILOX: the counter-based generator above.
+ * FPT_RNG_MT19937: Algorithm 2's generator, one MT19937 per replica seeded
+ * by the standard 32-bit initialization with (seed + replica index) mod 2^32
+ * (Sect. III.B); block j of a replica takes its outputs 4j .. 4j+3 and the
+ * same Box-Muller map.  Its 2.5 KB state per resident lane lives in the
+ * workspace.  MT19937 plans take one parameter set and one replica per lane;
+ * the server accepts only FPT_RNG_PHILOX jobs. */
+typedef enum { FPT_RNG_PHILOX = 0, FPT_RNG_MT19937 = 1 } fpt_rng;
+
 /* FPT_SCHED_REFILL: persistent lanes; a lane whose replica escaped or was
  * censored takes the next undrawn replica (the paper's "assign a new job to
  * the processor that has just completed", done on the device).
@@ -95,7 +104,7 @@ typedef struct fpt_params {
   int32_t model;        /* fpt_model */
   int32_t n_bins;       /* histogram bins, 1..FPT_MAX_BINS */
   int32_t scheme;       /* fpt_scheme (underdamped only; 0 for overdamped) */
-  int32_t reserved;     /* 0 */
+  int32_t rng;          /* fpt_rng */
   double alpha;         /* damping (underdamped), >= 0 */
   double T;             /* temperature, >= 0 (T = 0: noise-free) */
   double V0;            /* potential amplitude (1 in plasma units) */
@@ -109,7 +118,7 @@ typedef struct fpt_params {
   int64_t hist_k_max;   /* bins cover steps [1, hist_k_max]; 0: max_steps.
                            bin(k) = ((k-1) n_bins) div hist_k_max;
                            k > hist_k_max counts as overflow */
-  uint64_t seed;        /* Philox key */
+  uint64_t seed;        /* Philox key, or MT19937 base seed */
 } fpt_params;
 
 /* Launch tuning.  Zero fields are filled by the autotuner (cached per GPU
@@ -226,6 +235,16 @@ fpt_status fpt_rng_words(uint64_t seed, uint64_t replica0, int64_t n_rep,
                          uint64_t block0, int64_t n_blk, uint32_t* out,
                          void* stream);
 
+/* The MT19937 words the integrator draws in FPT_RNG_MT19937 mode: outputs
+ * 4b .. 4b+3 of the generator seeded with (seed + r) mod 2^32 for replicas
+ * r in [replica0, replica0+n_rep) and blocks b in [block0, block0+n_blk),
+ * laid out as fpt_rng_words; n_rep <= 2^24 and block0 + n_blk <= 2^24 (each
+ * lane generates every word up to the last block).  Allocates and frees
+ * n_rep * 2496 bytes of temporary device state and synchronizes `stream`. */
+fpt_status fpt_mt_words(uint64_t seed, uint64_t replica0, int64_t n_rep,
+                        uint64_t block0, int64_t n_blk, uint32_t* out,
+                        void* stream);
+
 /* The four normals of the same blocks, as the integrator of `precision`
  * computes them: out is device double (FPT_FP64) or float (FPT_FP32C). */
 fpt_status fpt_normals(uint64_t seed, uint64_t replica0, int64_t n_rep,
@@ -233,7 +252,9 @@ fpt_status fpt_normals(uint64_t seed, uint64_t replica0, int64_t n_rep,
                        void* out, void* stream);
 
 /* State (phi, v) after each of n_steps steps of one replica, no threshold:
- * out_phi / out_v device double[n_steps] (FP32C: phi_hi - c and v widened). */
+ * out_phi / out_v device double[n_steps] (FP32C: phi_hi - c and v widened).
+ * With params->rng = FPT_RNG_MT19937 the call allocates 2496 bytes of
+ * temporary device state and synchronizes `stream`. */
 fpt_status fpt_trajectory(const fpt_params* params, uint64_t replica,
                           int64_t n_steps, int32_t precision, double* out_phi,
                           double* out_v, void* stream);

@@ -29,6 +29,8 @@ FPT_UNDERDAMPED = 0
 FPT_OVERDAMPED = 1
 FPT_EXPLICIT = 0
 FPT_SEMI_IMPLICIT = 1
+FPT_RNG_PHILOX = 0
+FPT_RNG_MT19937 = 1
 FPT_FP64 = 0
 FPT_FP32C = 1
 FPT_SCHED_REFILL = 0
@@ -56,7 +58,7 @@ class FptParams(ctypes.Structure):
         ("model", ctypes.c_int32),
         ("n_bins", ctypes.c_int32),
         ("scheme", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("rng", ctypes.c_int32),
         ("alpha", ctypes.c_double),
         ("T", ctypes.c_double),
         ("V0", ctypes.c_double),
@@ -142,6 +144,8 @@ SIGNATURES = [
     ("fpt_server_destroy", None, [_VP]),
     ("fpt_rng_words", ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                      ctypes.c_uint64, ctypes.c_int64, _VP, _VP]),
+    ("fpt_mt_words", ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
+                                    ctypes.c_uint64, ctypes.c_int64, _VP, _VP]),
     ("fpt_normals", ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                    ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, _VP, _VP]),
     ("fpt_trajectory", ctypes.c_int, [ctypes.POINTER(FptParams), ctypes.c_uint64,
@@ -184,7 +188,7 @@ def check(status: int, allow=(FPT_OK,)) -> int:
 def make_params(p: Dict) -> FptParams:
     """fpt_params from a dict with the field names of include/fpt.h."""
     return FptParams(
-        int(p["model"]), int(p["n_bins"]), int(p.get("scheme", 0)), 0,
+        int(p["model"]), int(p["n_bins"]), int(p.get("scheme", 0)), int(p.get("rng", 0)),
         float(p["alpha"]), float(p["T"]),
         float(p.get("V0", 1.0)), float(p["gamma0"]), float(p["ramp"]), float(p["dt"]),
         float(p["phi0"]), float(p["v0"]), float(p["threshold"]), int(p["max_steps"]),
@@ -300,6 +304,11 @@ def fpt_server_destroy(server: int) -> None:
 def fpt_rng_words(seed, replica0, n_rep, block0, n_blk, out_ptr, stream) -> None:
     check(lib().fpt_rng_words(seed & (2**64 - 1), replica0, n_rep, block0, n_blk, out_ptr,
                               stream or None))
+
+
+def fpt_mt_words(seed, replica0, n_rep, block0, n_blk, out_ptr, stream) -> None:
+    check(lib().fpt_mt_words(seed & (2**64 - 1), replica0, n_rep, block0, n_blk, out_ptr,
+                             stream or None))
 
 
 def fpt_normals(seed, replica0, n_rep, block0, n_blk, precision, out_ptr, stream) -> None:

@@ -109,6 +109,15 @@ def rng_words(seed: int, replica0: int, n_rep: int, block0: int, n_blk: int) -> 
     return out[: n_rep * n_blk * 4].cpu().numpy().view(np.uint32).reshape(n_rep, n_blk, 4)
 
 
+def mt_words(seed: int, replica0: int, n_rep: int, block0: int, n_blk: int) -> np.ndarray:
+    """MT19937 words of the FPT_RNG_MT19937 mode, shaped (n_rep, n_blk, 4)."""
+    torch = _torch()
+    out = torch.empty(max(n_rep * n_blk * 4, 1), dtype=torch.int32, device="cuda")
+    _lib.fpt_mt_words(seed, replica0, n_rep, block0, n_blk, out.data_ptr(),
+                      torch.cuda.current_stream().cuda_stream)
+    return out[: n_rep * n_blk * 4].cpu().numpy().view(np.uint32).reshape(n_rep, n_blk, 4)
+
+
 def normals(seed: int, replica0: int, n_rep: int, block0: int, n_blk: int,
             precision="fp64") -> np.ndarray:
     torch = _torch()

@@ -146,7 +146,8 @@ fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
   TuneEntry best;
   bool have_rate = false;
   if (need_r || need_w || need_s) {
-    const std::string key = tune_key(arch, precision, model, t.schedule, multi);
+    const std::string key =
+        tune_key(arch, precision, model, t.schedule, multi) + (mt ? "/mt19937" : "");
     TuneEntry cached;
     if (tune_lookup(key, &cached)) {
       if (need_r) t.replicas_per_lane = cached.replicas_per_lane;

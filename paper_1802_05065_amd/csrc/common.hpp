@@ -50,4 +50,26 @@ constexpr int kMaxReplicasPerLane = 2;
 
 inline uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 
+// 16-byte groups of one slot's MT19937 state (624 words).
+constexpr uint64_t kMtGroupsPerSlot = 156;
+
+// Temporary device memory of a diagnostic call, freed on scope exit.
+struct DeviceBuffer {
+  void* ptr = nullptr;
+  DeviceBuffer() = default;
+  DeviceBuffer(const DeviceBuffer&) = delete;
+  DeviceBuffer& operator=(const DeviceBuffer&) = delete;
+  ~DeviceBuffer() {
+    if (ptr) (void)hipFree(ptr);
+  }
+  fpt_status alloc(size_t bytes) {
+    const hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return fail(FPT_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return FPT_OK;
+  }
+};
+
 }  // namespace fpt

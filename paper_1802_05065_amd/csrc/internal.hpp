@@ -81,6 +81,7 @@ struct SliceArgs {
   unsigned long long* st_j;
   unsigned long long* st_idx;
   uint32_t* st_set;
+  uint4* st_mt;                   // MT19937 state (156 groups per slot) or null
   unsigned long long n_lanes;
   unsigned long long* hist;
   MomDev* mom;

@@ -13,6 +13,10 @@
 // Without `refill` each slot keeps the replica assigned at the start
 // (one realization per thread, Algorithm 1's launch).
 //
+// With MT set the words of a block come from the replica's own MT19937
+// (Algorithm 2), whose state stays in device memory (mt19937.hpp); a slot
+// seeds it when it takes a new replica.
+//
 // Results (the escape-time / switching-current histograms of Sect. II.B and
 // IV.B): finished replicas write their step to the caller's array, then add
 // to a per-workgroup LDS hash table of (set, bin) counts and of per-set
@@ -27,6 +31,7 @@
 #include "device_math.hpp"
 #include "internal.hpp"
 #include "launch.hpp"
+#include "mt19937.hpp"
 
 namespace fpt {
 
@@ -346,8 +351,27 @@ __device__ __forceinline__ uint32_t blocks_to_cap(const Slot<FP64>& sl, uint64_t
   return wave_min_u32(left);
 }
 
-template <bool FP64, int MODEL, int R, bool MULTI>
+// The 4 words of a slot's next block: Philox keyed by (block, replica), or
+// the next 4 outputs of the replica's MT19937 (active lanes only: a free
+// slot's state is re-seeded when it takes a replica).
+template <bool MT, bool FP64>
+__device__ __forceinline__ Words block_words(const SliceArgs& a, uint64_t n_slots,
+                                             uint64_t slot, bool active, MtCarry& mc,
+                                             const Slot<FP64>& sl, uint32_t k0,
+                                             uint32_t k1) {
+  if constexpr (MT) {
+    Words w{0u, 0u, 0u, 0u};
+    if (active) w = mt_block(a.st_mt, n_slots, slot, mc);
+    return w;
+  } else {
+    return philox4x32_10((uint32_t)sl.j, (uint32_t)(sl.j >> 32), (uint32_t)sl.idx,
+                         (uint32_t)(sl.idx >> 32), k0, k1);
+  }
+}
+
+template <bool FP64, int MODEL, int R, bool MULTI, bool MT>
 __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
+  static_assert(!MT || (R == 1 && !MULTI), "MT19937 mode: one set, one slot per lane");
   __shared__ LdsTables tab;
   for (int i = threadIdx.x; i < kHistSlots; i += kBlockThreads) {
     tab.h_key[i] = kEmpty;
@@ -379,11 +403,19 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
   // its active lanes can run before one reaches its step cap
   uint64_t amask[R];
   uint32_t safe[R];
+  MtCarry mc[R];
+  const uint64_t n_slots = a.n_lanes * (uint64_t)R;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     restore_slot(a, (uint64_t)r * a.n_lanes + lane_g, s[r]);
     const bool act = s[r].set != kInactive;
     if (MULTI && act) load_params(s[r], a.sets[s[r].set]);
+    if constexpr (MT) {
+      mc[r] = MtCarry{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), 0u};
+      if (act)
+        mc[r] = mt_load(a.st_mt, n_slots, (uint64_t)r * a.n_lanes + lane_g,
+                        (uint32_t)(s[r].j % kMtGroups));
+    }
     amask[r] = __ballot(act);
     safe[r] = blocks_to_cap(s[r], MULTI ? s[r].jmax : uni.jmax, act);
   }
@@ -414,6 +446,11 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
               const SetDev& sd = a.sets[set];
               start_replica(s[r], set, idx, sd);
               if (MULTI) load_params(s[r], sd);
+              if constexpr (MT) {
+                const uint64_t slot = (uint64_t)r * a.n_lanes + lane_g;
+                mt_seed_slot(a.st_mt, n_slots, slot, mt_replica_seed(sd.seed, idx));
+                mc[r] = mt_load(a.st_mt, n_slots, slot, 0u);
+              }
               assigned = true;
             }
           }
@@ -439,9 +476,9 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
       for (int r = 0; r < R; ++r) {
         Slot<FP64>& sl = s[r];
         const auto& p = MULTI ? sl.p : uni.p;
-        const Words w = philox4x32_10((uint32_t)sl.j, (uint32_t)(sl.j >> 32),
-                                      (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32),
-                                      MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
+        const Words w = block_words<MT>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
+                                        (amask[r] & lane_bit) != 0, mc[r], sl,
+                                        MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
         double z[4];
         normals_f64(w, z);
 #pragma unroll
@@ -466,9 +503,9 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
       for (int r = 0; r < R; ++r) {
         Slot<FP64>& sl = s[r];
         const auto& p = MULTI ? sl.p : uni.p;
-        const Words w = philox4x32_10((uint32_t)sl.j, (uint32_t)(sl.j >> 32),
-                                      (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32),
-                                      MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
+        const Words w = block_words<MT>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
+                                        (amask[r] & lane_bit) != 0, mc[r], sl,
+                                        MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
         bm[r] = box_muller_f32(w);
         g0[r] = block_g_f32(p.gB, sl.kd, MULTI ? p.gA : gA_uni);
         zs[r][0] = p.sig * bm[r].radius[0];
@@ -603,6 +640,8 @@ __global__ __launch_bounds__(kBlockThreads) void init_kernel(SliceArgs a,
   uint64_t idx;
   if (slot < n_assign && map_flat(a, slot, &set, &idx)) {
     start_replica(s, set, idx, a.sets[set]);
+    if (a.st_mt)
+      mt_seed_slot(a.st_mt, n_slots, slot, mt_replica_seed(a.sets[set].seed, idx));
   }
   store_slot(a, slot, s);
 }
@@ -646,15 +685,39 @@ __global__ void normals_kernel(uint64_t seed, uint64_t replica0, uint64_t n_rep,
   }
 }
 
+// One lane per replica, state at st (n_rep slots).
+__global__ void mt_words_kernel(uint64_t seed, uint64_t replica0, uint64_t n_rep,
+                                uint64_t block0, uint64_t n_blk, uint4* st,
+                                uint32_t* out) {
+  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rep) return;
+  mt_seed_slot(st, n_rep, r, mt_replica_seed(seed, replica0 + r));
+  MtCarry mc = mt_load(st, n_rep, r, 0u);
+  for (uint64_t b = 0; b < block0 + n_blk; ++b) {
+    const Words w = mt_block(st, n_rep, r, mc);
+    if (b < block0) continue;
+    uint32_t* o = out + 4 * (r * n_blk + (b - block0));
+    o[0] = w.w0;
+    o[1] = w.w1;
+    o[2] = w.w2;
+    o[3] = w.w3;
+  }
+}
+
 template <bool FP64, int MODEL>
 __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
-                                  double* out_phi, double* out_v) {
+                                  double* out_phi, double* out_v, uint4* mt) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Slot<FP64> s;
   start_replica(s, 0, replica, sd);
   load_params(s, sd);
+  MtCarry mc{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), 0u};
+  if (mt) {
+    mt_seed_slot(mt, 1, 0, mt_replica_seed(sd.seed, replica));
+    mc = mt_load(mt, 1, 0, 0u);
+  }
   for (int64_t k0 = 0; k0 < n_steps; k0 += 4) {
-    const Words w = replica_words(sd.seed, replica, s.j);
+    const Words w = mt ? mt_block(mt, 1, 0, mc) : replica_words(sd.seed, replica, s.j);
     if constexpr (FP64) {
       double z[4];
       normals_f64(w, z);
@@ -696,10 +759,10 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
 // ---------------------------------------------------------------------------
 // Host-side launchers
 
-template <bool FP64, int MODEL, int R, bool MULTI>
+template <bool FP64, int MODEL, int R, bool MULTI, bool MT = false>
 static hipError_t launch_slice_t(const SliceArgs& a, uint32_t n_groups,
                                  hipStream_t st) {
-  hipLaunchKernelGGL((slice_kernel<FP64, MODEL, R, MULTI>), dim3(n_groups),
+  hipLaunchKernelGGL((slice_kernel<FP64, MODEL, R, MULTI, MT>), dim3(n_groups),
                      dim3(kBlockThreads), 0, st, a);
   return hipGetLastError();
 }
@@ -714,6 +777,10 @@ static hipError_t launch_slice_m(bool multi, const SliceArgs& a, uint32_t n_grou
 template <bool FP64, int MODEL>
 static hipError_t launch_slice_r(int R, bool multi, const SliceArgs& a,
                                  uint32_t n_groups, hipStream_t st) {
+  if (a.st_mt) {
+    if (R != 1 || multi) return hipErrorInvalidValue;
+    return launch_slice_t<FP64, MODEL, 1, false, true>(a, n_groups, st);
+  }
   return R == 2 ? launch_slice_m<FP64, MODEL, 2>(multi, a, n_groups, st)
                 : launch_slice_m<FP64, MODEL, 1>(multi, a, n_groups, st);
 }
@@ -788,31 +855,40 @@ hipError_t launch_normals(bool fp64, uint64_t seed, uint64_t replica0,
 template <bool FP64>
 static void launch_trajectory_t(int kind, const SetDev& sd, uint64_t replica,
                                 int64_t n_steps, double* out_phi, double* out_v,
-                                hipStream_t st) {
+                                uint4* mt, hipStream_t st) {
   switch (kind) {
     case kOver:
       hipLaunchKernelGGL((trajectory_kernel<FP64, kOver>), dim3(1), dim3(64), 0, st, sd,
-                         replica, n_steps, out_phi, out_v);
+                         replica, n_steps, out_phi, out_v, mt);
       break;
     case kUnderSemiImplicit:
       hipLaunchKernelGGL((trajectory_kernel<FP64, kUnderSemiImplicit>), dim3(1), dim3(64), 0,
-                         st, sd, replica, n_steps, out_phi, out_v);
+                         st, sd, replica, n_steps, out_phi, out_v, mt);
       break;
     default:
       hipLaunchKernelGGL((trajectory_kernel<FP64, kUnderExplicit>), dim3(1), dim3(64), 0, st,
-                         sd, replica, n_steps, out_phi, out_v);
+                         sd, replica, n_steps, out_phi, out_v, mt);
   }
 }
 
 hipError_t launch_trajectory(bool fp64, int kind, const SetDev& sd,
                              uint64_t replica, int64_t n_steps, double* out_phi,
-                             double* out_v, hipStream_t st) {
+                             double* out_v, uint4* mt, hipStream_t st) {
   if (n_steps <= 0) return hipSuccess;
   if (fp64) {
-    launch_trajectory_t<true>(kind, sd, replica, n_steps, out_phi, out_v, st);
+    launch_trajectory_t<true>(kind, sd, replica, n_steps, out_phi, out_v, mt, st);
   } else {
-    launch_trajectory_t<false>(kind, sd, replica, n_steps, out_phi, out_v, st);
+    launch_trajectory_t<false>(kind, sd, replica, n_steps, out_phi, out_v, mt, st);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_mt_words(uint64_t seed, uint64_t replica0, uint64_t n_rep,
+                           uint64_t block0, uint64_t n_blk, uint4* state,
+                           uint32_t* out, hipStream_t st) {
+  if (n_rep == 0 || n_blk == 0) return hipSuccess;
+  hipLaunchKernelGGL(mt_words_kernel, dim3((uint32_t)((n_rep + 63) / 64)), dim3(64), 0, st,
+                     seed, replica0, n_rep, block0, n_blk, state, out);
   return hipGetLastError();
 }
 

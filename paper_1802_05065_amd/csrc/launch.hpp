@@ -10,6 +10,7 @@
 namespace fpt {
 
 // `kind`: integrator kind (kUnderExplicit, kOver, kUnderSemiImplicit).
+// a.st_mt non-null selects the MT19937 kernels (R = 1, single set only).
 hipError_t launch_slice(bool fp64, int kind, int R, bool multi,
                         const SliceArgs& a, uint32_t n_groups, hipStream_t st);
 hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,
@@ -22,8 +23,13 @@ hipError_t launch_rng_words(uint64_t seed, uint64_t replica0, uint64_t n_rep,
 hipError_t launch_normals(bool fp64, uint64_t seed, uint64_t replica0,
                           uint64_t n_rep, uint64_t block0, uint64_t n_blk,
                           void* out, hipStream_t st);
+// `mt`: 2496 bytes of MT19937 state (FPT_RNG_MT19937), else null.
 hipError_t launch_trajectory(bool fp64, int kind, const SetDev& sd,
                              uint64_t replica, int64_t n_steps, double* out_phi,
-                             double* out_v, hipStream_t st);
+                             double* out_v, uint4* mt, hipStream_t st);
+// `state`: n_rep * 2496 bytes.
+hipError_t launch_mt_words(uint64_t seed, uint64_t replica0, uint64_t n_rep,
+                           uint64_t block0, uint64_t n_blk, uint4* state,
+                           uint32_t* out, hipStream_t st);
 
 }  // namespace fpt

@@ -18,6 +18,7 @@ struct Plan {
   int precision = FPT_FP64;
   int model = kUnderExplicit;   // integrator kind
   bool multi = false;
+  bool mt = false;              // FPT_RNG_MT19937: per-slot generator state
   fpt_tuning tuning_req{};      // as given (zeros: autotune)
   fpt_tuning tuning{};          // as used by the last simulate
   uint64_t total_replicas = 0;
@@ -30,6 +31,7 @@ struct Plan {
   uint64_t max_slots = 0;
   uint64_t off_sets = 0, off_chunks = 0, off_ctr = 0, off_mom = 0, off_hist = 0;
   uint64_t off_st_phi = 0, off_st_v = 0, off_st_j = 0, off_st_idx = 0, off_st_set = 0;
+  uint64_t off_st_mt = 0;
   uint64_t ws_bytes = 0;
 
   // last run

@@ -46,6 +46,8 @@ fpt_status validate_params(const fpt_params& p, int i) {
                 p.scheme);
   if (p.model == FPT_OVERDAMPED && p.scheme != FPT_EXPLICIT)
     return fail(FPT_E_INVAL, "set %d: the overdamped model has only scheme 0", i);
+  if (p.rng != FPT_RNG_PHILOX && p.rng != FPT_RNG_MT19937)
+    return fail(FPT_E_INVAL, "set %d: rng %d is not 0 (Philox) or 1 (MT19937)", i, p.rng);
   if (p.n_bins < 1 || p.n_bins > FPT_MAX_BINS)
     return fail(FPT_E_INVAL, "set %d: n_bins %d outside [1, %d]", i, p.n_bins, FPT_MAX_BINS);
   if (!(p.dt > 0.0) || !std::isfinite(p.dt))
@@ -168,10 +170,11 @@ fpt_status Plan::layout() {
   cus = di.cus;
   arch = di.arch;
   uint64_t slots;
+  const uint64_t max_r = mt ? 1 : kMaxReplicasPerLane;
   if (tuning_req.schedule == FPT_SCHED_ONE_PER_LANE) {
-    slots = round_up(std::max<uint64_t>(total_flat, 1), kBlockThreads * kMaxReplicasPerLane);
+    slots = round_up(std::max<uint64_t>(total_flat, 1), kBlockThreads * max_r);
   } else {
-    slots = (uint64_t)cus * 4 * kMaxWavesPerSimd * kWave * kMaxReplicasPerLane;
+    slots = (uint64_t)cus * 4 * kMaxWavesPerSimd * kWave * max_r;
   }
   max_slots = slots;
   uint64_t off = 0;
@@ -195,6 +198,8 @@ fpt_status Plan::layout() {
   off = align256(off + 8 * slots);
   off_st_set = off;
   off = align256(off + 4 * slots);
+  off_st_mt = off;
+  if (mt) off = align256(off + sizeof(uint4) * kMtGroupsPerSlot * slots);
   ws_bytes = off;
   return FPT_OK;
 }
@@ -212,6 +217,7 @@ SliceArgs Plan::slice_args(char* ws, uint64_t* hist_dev, uint64_t n_lanes_) cons
   a.st_j = reinterpret_cast<unsigned long long*>(ws + off_st_j);
   a.st_idx = reinterpret_cast<unsigned long long*>(ws + off_st_idx);
   a.st_set = reinterpret_cast<uint32_t*>(ws + off_st_set);
+  a.st_mt = mt ? reinterpret_cast<uint4*>(ws + off_st_mt) : nullptr;
   a.n_lanes = n_lanes_;
   a.hist = reinterpret_cast<unsigned long long*>(hist_dev);
   a.mom = reinterpret_cast<MomDev*>(ws + off_mom);
@@ -482,6 +488,9 @@ fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision
     if (integrator_kind(params[i]) != integrator_kind(params[0]))
       return fail(FPT_E_INVAL, "set %d: all sets of a plan must share one model and scheme",
                   i);
+  const bool mt = params[0].rng == FPT_RNG_MT19937;
+  if (mt && n_sets > 1)
+    return fail(FPT_E_INVAL, "an MT19937 (rng 1) plan takes one parameter set");
   fpt_tuning t{};
   if (tuning) t = *tuning;
   if (t.schedule != FPT_SCHED_REFILL && t.schedule != FPT_SCHED_ONE_PER_LANE)
@@ -492,12 +501,18 @@ fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision
     return fail(FPT_E_INVAL, "tuning.waves_per_simd must be in [0, %d]", kMaxWavesPerSimd);
   if (t.steps_per_launch < 0 || t.steps_per_launch % 4 || t.steps_per_launch > (1 << 26))
     return fail(FPT_E_INVAL, "tuning.steps_per_launch must be a multiple of 4 in [0, 2^26]");
+  if (mt) {
+    if (t.replicas_per_lane > 1)
+      return fail(FPT_E_INVAL, "an MT19937 plan runs one replica per lane");
+    t.replicas_per_lane = 1;
+  }
 
   Plan* p = new Plan();
   p->precision = precision;
   p->model = integrator_kind(params[0]);
   p->tuning_req = t;
   p->multi = n_sets > 1;
+  p->mt = mt;
   uint64_t off = 0;
   for (int32_t i = 0; i < n_sets; ++i) {
     p->params.push_back(params[i]);
@@ -614,8 +629,34 @@ fpt_status fpt_trajectory(const fpt_params* params, uint64_t replica, int64_t n_
     return fpt::fail(FPT_E_INVAL, "precision %d unknown", precision);
   FPT_TRY(fpt::validate_params(*params, 0));
   const fpt::SetDev sd = fpt::derive_set(*params);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (params->rng != FPT_RNG_MT19937 || n_steps == 0) {
+    FPT_HIP(fpt::launch_trajectory(precision == FPT_FP64, (int)sd.model, sd, replica,
+                                   n_steps, out_phi, out_v, nullptr, st));
+    return FPT_OK;
+  }
+  fpt::DeviceBuffer state;
+  FPT_TRY(state.alloc(sizeof(uint4) * fpt::kMtGroupsPerSlot));
   FPT_HIP(fpt::launch_trajectory(precision == FPT_FP64, (int)sd.model, sd, replica, n_steps,
-                                 out_phi, out_v, static_cast<hipStream_t>(stream)));
+                                 out_phi, out_v, static_cast<uint4*>(state.ptr), st));
+  FPT_HIP(hipStreamSynchronize(st));
+  return FPT_OK;
+}
+
+fpt_status fpt_mt_words(uint64_t seed, uint64_t replica0, int64_t n_rep, uint64_t block0,
+                        int64_t n_blk, uint32_t* out, void* stream) {
+  if (n_rep < 0 || n_blk < 0 || (n_rep * n_blk > 0 && !out))
+    return fpt::fail(FPT_E_INVAL, "bad sizes or NULL output");
+  if (n_rep > (int64_t(1) << 24) || block0 > (uint64_t(1) << 24) ||
+      (uint64_t)n_blk > (uint64_t(1) << 24) - block0)
+    return fpt::fail(FPT_E_INVAL, "n_rep above 2^24 or blocks beyond 2^24");
+  if (n_rep == 0 || n_blk == 0) return FPT_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  fpt::DeviceBuffer state;
+  FPT_TRY(state.alloc(sizeof(uint4) * fpt::kMtGroupsPerSlot * (uint64_t)n_rep));
+  FPT_HIP(fpt::launch_mt_words(seed, replica0, (uint64_t)n_rep, block0, (uint64_t)n_blk,
+                               static_cast<uint4*>(state.ptr), out, st));
+  FPT_HIP(hipStreamSynchronize(st));
   return FPT_OK;
 }
 

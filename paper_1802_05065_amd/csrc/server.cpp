@@ -415,6 +415,8 @@ fpt_status fpt_submit(fpt_server_t server, const fpt_params* params, uint64_t* j
   if (!server || !params || !job_id) return fpt::fail(FPT_E_INVAL, "NULL argument");
   fpt::Server* s = server->impl;
   FPT_TRY(fpt::validate_params(*params, 0));
+  if (params->rng != FPT_RNG_PHILOX)
+    return fpt::fail(FPT_E_INVAL, "the server runs Philox jobs only (rng 0)");
   if (params->model != s->model || params->scheme != FPT_EXPLICIT)
     return fpt::fail(FPT_E_INVAL, "job model %d / scheme %d: this server runs model %d with "
                      "the explicit scheme", params->model, params->scheme, s->model);

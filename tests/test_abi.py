@@ -64,6 +64,7 @@ def test_plan_accepts_workloads_without_gpu(lib):
     ("alpha", -0.1, "alpha"),
     ("threshold", math.inf, "threshold"),
     ("scheme", 2, "scheme"),
+    ("rng", 2, "rng"),
 ])
 def test_plan_rejects_bad_params(lib, field, value, needle):
     p = workloads.plain_escape()
@@ -140,3 +141,22 @@ def test_workspace_grows_with_one_per_lane_schedule(lib):
     finally:
         _lib.fpt_plan_destroy(h1)
         _lib.fpt_plan_destroy(h2)
+
+
+def test_mt19937_plans(lib):
+    p = dict(workloads.plain_escape(n_replicas=5000), rng=1)
+    h = _lib.fpt_plan([p], "fp32c")
+    h0 = _lib.fpt_plan([dict(p, rng=0)], "fp32c")
+    try:
+        # 624 words of generator state per slot, one slot per lane
+        extra = _lib.fpt_plan_workspace(h) - _lib.fpt_plan_workspace(h0)
+        assert extra >= 2496 * 256 * 4 * 8 * 64 // 2
+    finally:
+        _lib.fpt_plan_destroy(h)
+        _lib.fpt_plan_destroy(h0)
+    with pytest.raises(_lib.FptError) as e:
+        _lib.fpt_plan([p, p], "fp64")
+    assert "one parameter set" in e.value.message
+    with pytest.raises(_lib.FptError) as e:
+        _lib.fpt_plan([p], "fp64", dict(replicas_per_lane=2))
+    assert "one replica per lane" in e.value.message
