@@ -178,6 +178,38 @@ def test_underdamped_free_velocity_is_ar1(oracle_mod, scheme):
 # (the exact flow: e^{-alpha h}).
 
 
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_stationary_temperature_in_the_well(oracle_mod, scheme):
+    # small oscillations at the well bottom form a linear stochastic
+    # recursion whose stationary covariance solves the discrete Lyapunov
+    # equation (scipy); explicit Euler heats the well by about
+    # alpha / (alpha - dt omega^2), the semi-implicit scheme does not
+    from scipy.linalg import solve_discrete_lyapunov
+
+    g, alpha, T, h = 0.5, 0.2, 0.002, 0.05
+    w2 = math.sqrt(1 - g * g)
+    if scheme == 0:
+        A, b = np.array([[1, h], [-h * w2, 1 - h * alpha]]), np.array([0.0, 1.0])
+    else:
+        A = np.array([[1 - h * h * w2, h * (1 - h * alpha)], [-h * w2, 1 - h * alpha]])
+        b = np.array([h, 1.0])
+    C = solve_discrete_lyapunov(A, 2 * alpha * T * h * np.outer(b, b))
+    op = oracle_mod.OracleParams(model=0, alpha=alpha, T=T, V0=1.0, gamma0=g, ramp=0.0, dt=h,
+                                 phi0=math.asin(g), v0=0.0, threshold=1e9,
+                                 max_steps=10, seed=17, scheme=scheme)
+    n = 2_000_000
+    phi, v = oracle_mod.trajectory(op, 0, n)
+    phi, v = phi[5000:], v[5000:]
+    t_phi = w2 * phi.var() / T
+    t_v = (v * v).mean() / T
+    print(f"scheme {scheme}: omega^2<dphi^2>/T = {t_phi:.4f} (linear {w2 * C[0, 0] / T:.4f}), "
+          f"<v^2>/T = {t_v:.4f} (linear {C[1, 1] / T:.4f})")
+    assert t_phi == pytest.approx(w2 * C[0, 0] / T, rel=0.04)
+    assert t_v == pytest.approx(C[1, 1] / T, rel=0.04)
+    if scheme == 0:
+        assert w2 * C[0, 0] / T > 1.2  # the explicit scheme is measurably hot here
+
+
 @pytest.mark.parametrize("scheme,factor", [
     (0, lambda h, a: 1.0 - h * a + h * h),   # Algorithm 1: explicit
     (1, lambda h, a: 1.0 - h * a),           # semi-implicit (symplectic) variant
