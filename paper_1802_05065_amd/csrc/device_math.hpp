@@ -122,13 +122,14 @@ struct ParF64 {
 };
 
 // FP32C constants, phase in revolutions (phi / 2 pi):
-//   underdamped  v_k = damp v + G_k - kS sin(2 pi phr) + sig z_k,
+//   underdamped  v_k = damp v + G_k + nkS sin(2 pi phr) + sig z_k,
 //                phr_k = phr + h_rev v            (Kahan-compensated)
-//   overdamped   phr_k = phr + G_k - kS sin(2 pi phr) + sig z_k  (compensated)
-// with G_k = gA + gB k evaluated in FP64 from the exact step k.
+//   overdamped   phr_k = phr + G_k + nkS sin(2 pi phr) + sig z_k  (compensated)
+// with G_k = gA + gB k evaluated in FP64 from the exact step k, nkS = -kS,
+// and dG, dG2, dG3 the bias offsets of a block's steps 2, 3, 4 from its first.
 struct ParF32 {
   double gA, gB, th_rev;
-  float h_rev, damp, kS, sig, dG, th_near_rev;
+  float h_rev, damp, nkS, sig, dG, dG2, dG3, th_near_rev;
 };
 
 __device__ __forceinline__ ParF64 load_par_f64(const SetDev& s) {
@@ -136,8 +137,8 @@ __device__ __forceinline__ ParF64 load_par_f64(const SetDev& s) {
 }
 
 __device__ __forceinline__ ParF32 load_par_f32(const SetDev& s) {
-  return ParF32{s.gA, s.gB, s.th_rev, s.h_rev_f, s.damp_f, s.kS_f, s.sig_f, s.dG_f,
-                s.th_near_rev_f};
+  return ParF32{s.gA, s.gB, s.th_rev, s.h_rev_f, s.damp_f, s.nkS_f, s.sig_f, s.dG_f,
+                s.dG2_f, s.dG3_f, s.th_near_rev_f};
 }
 
 // ---------------------------------------------------------------------------
@@ -176,57 +177,82 @@ __device__ __forceinline__ void step_f64_over(const ParF64& p, double kd,
   phi = phi + p.dt * drift + p.sigma * r;
 }
 
-// FP32C underdamped step q (0..3) of a block.  The phase is the compensated
-// pair (phr, c) in revolutions with true value phr - c (Kahan summation of the
-// increments h_rev v); `g` is G_k rounded once to FP32; `zs` is the noise
-// factor sig*radius' and `trig` the cos or sin of the pair's angle.
-__device__ __forceinline__ void step_f32_under(const ParF32& p, float g, float zs,
-                                               float trig, float& phr, float& c,
-                                               float& v) {
-  const float s = __builtin_amdgcn_sinf(phr);
-  const float y = __builtin_fmaf(p.h_rev, v, -c);
+// FP32C steps.  The phase is the compensated pair (phr, e) in revolutions
+// with true value phr + e (Kahan summation of the increments, the error term
+// kept with the sign that makes every update an accumulation).  `a` enters
+// as G_k rounded to FP32 and is consumed; `zs` is the noise factor
+// sig*radius' and `trig` the cos or sin of the pair's angle.  Each update is
+// a multiply-add into a value that dies with it, so the compiler can use the
+// two-operand v_fmac_f32, which issues at twice the rate of the
+// three-operand v_fma_f32 on gfx950.
+
+// Compensated phr += inc, given y = inc + e; returns y.  The new error term
+// is y - (phr_new - phr_old), so it can be recomputed exactly from y and the
+// two phases (kahan_error).
+__device__ __forceinline__ float kahan_add(float y, float& phr, float& e) {
   const float t = phr + y;
-  c = (t - phr) - y;
+  e = y - (t - phr);
   phr = t;
-  const float inc = __builtin_fmaf(-p.kS, s, __builtin_fmaf(zs, trig, g));
-  v = __builtin_fmaf(p.damp, v, inc);
+  return y;
 }
 
-// FP32C underdamped, semi-implicit: the velocity first, then the phase moves
-// with the new velocity.
-__device__ __forceinline__ void step_f32_under_si(const ParF32& p, float g, float zs,
-                                                  float trig, float& phr, float& c,
-                                                  float& v) {
-  const float s = __builtin_amdgcn_sinf(phr);
-  const float inc = __builtin_fmaf(-p.kS, s, __builtin_fmaf(zs, trig, g));
-  v = __builtin_fmaf(p.damp, v, inc);
-  const float y = __builtin_fmaf(p.h_rev, v, -c);
-  const float t = phr + y;
-  c = (t - phr) - y;
-  phr = t;
+__device__ __forceinline__ float kahan_error(float y, float phr_new, float phr_old) {
+  return y - (phr_new - phr_old);
 }
 
-// FP32C overdamped: the increment G_k - kS sin(2 pi phr) + sig z_k is added
-// to the compensated phase.
-__device__ __forceinline__ void step_f32_over(const ParF32& p, float g, float zs,
-                                              float trig, float& phr, float& c) {
+// Underdamped, explicit (Algorithm 1): phase from the old velocity.
+__device__ __forceinline__ float step_f32_under(const ParF32& p, float a, float zs,
+                                                float trig, float& phr, float& e,
+                                                float& v) {
   const float s = __builtin_amdgcn_sinf(phr);
-  const float inc = __builtin_fmaf(-p.kS, s, __builtin_fmaf(zs, trig, g));
-  const float y = inc - c;
-  const float t = phr + y;
-  c = (t - phr) - y;
-  phr = t;
+  const float y = kahan_add(__builtin_fmaf(p.h_rev, v, e), phr, e);
+  a = __builtin_fmaf(zs, trig, a);
+  a = __builtin_fmaf(p.nkS, s, a);
+  v = __builtin_fmaf(p.damp, v, a);
+  return y;
 }
 
-// G_k of the block's first step, from the exact step count k1 = 4 j + 1.
-__device__ __forceinline__ float block_g_f32(double gB, double k1, double gA) {
-  return (float)__builtin_fma(gB, k1, gA);
+// Underdamped, semi-implicit: the velocity first, then the phase moves with
+// the new velocity.
+__device__ __forceinline__ float step_f32_under_si(const ParF32& p, float a, float zs,
+                                                   float trig, float& phr, float& e,
+                                                   float& v) {
+  const float s = __builtin_amdgcn_sinf(phr);
+  a = __builtin_fmaf(zs, trig, a);
+  a = __builtin_fmaf(p.nkS, s, a);
+  v = __builtin_fmaf(p.damp, v, a);
+  return kahan_add(__builtin_fmaf(p.h_rev, v, e), phr, e);
+}
+
+// Overdamped: the increment G_k - kS sin(2 pi phr) + sig z_k is added to the
+// compensated phase.
+__device__ __forceinline__ float step_f32_over(const ParF32& p, float a, float zs,
+                                               float trig, float& phr, float& e) {
+  const float s = __builtin_amdgcn_sinf(phr);
+  a = __builtin_fmaf(zs, trig, a);
+  a = __builtin_fmaf(p.nkS, s, a);
+  return kahan_add(a + e, phr, e);
+}
+
+// Bias terms G_k of a block's 4 steps: the first from the exact step count
+// k1 = 4 j + 1 in FP64, the others by FP32 offsets.
+struct BlockG {
+  float g[4];
+};
+
+__device__ __forceinline__ BlockG block_g4(const ParF32& p, double k1, double gA) {
+  BlockG b;
+  b.g[0] = (float)__builtin_fma(p.gB, k1, gA);
+  b.g[1] = b.g[0] + p.dG;
+  b.g[2] = b.g[0] + p.dG2;
+  b.g[3] = b.g[0] + p.dG3;
+  return b;
 }
 
 // Test of the compensated phase against the FP64 threshold (revolutions):
-// phr - c formed in FP64 holds the compensated value to FP64 rounding.
-__device__ __forceinline__ bool above_f64(float phr, float c, double th_rev) {
-  return ((double)phr - (double)c) > th_rev;
+// phr + e formed in FP64 holds the compensated value to FP64 rounding.
+__device__ __forceinline__ bool above_f64(float phr, float e, double th_rev) {
+  return ((double)phr + (double)e) > th_rev;
 }
 
 }  // namespace fpt

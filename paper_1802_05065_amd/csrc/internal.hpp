@@ -37,7 +37,10 @@ struct alignas(16) SetDev {
   // FP32C constants (phase in revolutions, phi / 2 pi): bias term
   // G_k = gA + gB k in FP64, threshold, and FP32 step coefficients
   double gA, gB, th_rev;
-  float h_rev_f, damp_f, kS_f, sig_f, dG_f, th_near_rev_f, phr0_f, c0_f, v0_f, pad_f;
+  // (nkS_f = -kS; dG2_f, dG3_f = 2 and 3 bias increments; e0_f: initial
+  // phase error, true phase = phr0_f + e0_f)
+  float h_rev_f, damp_f, nkS_f, sig_f, dG_f, dG2_f, dG3_f, th_near_rev_f, phr0_f, e0_f, v0_f,
+      pad_f;
   int64_t max_steps;    // klim
   uint64_t jmax;        // block of the last allowed step: (max_steps - 1) / 4
   int64_t k_hist;       // histogram covers steps [1, k_hist]

@@ -47,7 +47,7 @@ struct Slot<true> {
   uint64_t idx, j;
   double kd;  // 4 j + 1, the step number of the block's first step (exact)
   double phi, v;
-  float c;    // unused in FP64
+  float e;    // unused in FP64
   ParF64 p;
   uint32_t k0, k1;
   uint64_t jmax;
@@ -59,7 +59,7 @@ struct Slot<false> {
   uint64_t idx, j;
   double kd;
   float phi, v;  // phi: phase in revolutions
-  float c;       // its Kahan compensation
+  float e;       // its Kahan error term: true phase = phi + e
   ParF32 p;
   uint32_t k0, k1;
   uint64_t jmax;
@@ -87,16 +87,16 @@ __device__ __forceinline__ void start_replica(Slot<FP64>& s, uint32_t set,
   if constexpr (FP64) {
     s.phi = sd.phi0;
     s.v = sd.v0;
-    s.c = 0.0f;
+    s.e = 0.0f;
   } else {
     s.phi = sd.phr0_f;
-    s.c = sd.c0_f;
+    s.e = sd.e0_f;
     s.v = sd.v0_f;
   }
 }
 
 // Resident-state encoding: st_phi holds the FP64 phase, or the FP32 pair
-// (phi, c) in the low / high word; st_v the FP64 or FP32 velocity.
+// (phi, e) in the low / high word; st_v the FP64 or FP32 velocity.
 template <bool FP64>
 __device__ __forceinline__ void store_slot(const SliceArgs& a, uint64_t slot,
                                            const Slot<FP64>& s) {
@@ -109,7 +109,7 @@ __device__ __forceinline__ void store_slot(const SliceArgs& a, uint64_t slot,
     a.st_v[slot] = (unsigned long long)__double_as_longlong(s.v);
   } else {
     a.st_phi[slot] = (unsigned long long)__float_as_uint(s.phi) |
-                     ((unsigned long long)__float_as_uint(s.c) << 32);
+                     ((unsigned long long)__float_as_uint(s.e) << 32);
     a.st_v[slot] = (unsigned long long)__float_as_uint(s.v);
   }
 }
@@ -123,7 +123,7 @@ __device__ __forceinline__ void restore_slot(const SliceArgs& a, uint64_t slot,
   s.kd = 0.0;
   s.phi = 0;
   s.v = 0;
-  s.c = 0.0f;
+  s.e = 0.0f;
   if (s.set == kInactive) return;
   s.idx = a.st_idx[slot];
   s.j = a.st_j[slot];
@@ -133,10 +133,10 @@ __device__ __forceinline__ void restore_slot(const SliceArgs& a, uint64_t slot,
   if constexpr (FP64) {
     s.phi = __longlong_as_double((long long)ph);
     s.v = __longlong_as_double((long long)vv);
-    s.c = 0.0f;
+    s.e = 0.0f;
   } else {
     s.phi = __uint_as_float((uint32_t)ph);
-    s.c = __uint_as_float((uint32_t)(ph >> 32));
+    s.e = __uint_as_float((uint32_t)(ph >> 32));
     s.v = __uint_as_float((uint32_t)vv);
   }
 }
@@ -498,7 +498,8 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
       // generator and normals of every slot first, then the 4 steps with the
       // slots interleaved (independent chains for the scheduler)
       BoxMullerF32 bm[R];
-      float g0[R], zs[R][2];
+      BlockG gk[R];
+      float zs[R][2];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         Slot<FP64>& sl = s[r];
@@ -507,41 +508,55 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
                                         (amask[r] & lane_bit) != 0, mc[r], sl,
                                         MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
         bm[r] = box_muller_f32(w);
-        g0[r] = block_g_f32(p.gB, sl.kd, MULTI ? p.gA : gA_uni);
+        gk[r] = block_g4(p, sl.kd, MULTI ? p.gA : gA_uni);
+        // all four bias terms exist before the first step, so every step can
+        // accumulate into its own (the first otherwise still feeds the rest)
+        asm volatile("" : "+v"(gk[r].g[0]), "+v"(gk[r].g[1]), "+v"(gk[r].g[2]),
+                     "+v"(gk[r].g[3]));
         zs[r][0] = p.sig * bm[r].radius[0];
         zs[r][1] = p.sig * bm[r].radius[1];
       }
-      float ph_q[R][4], c_q[R][4];
-      uint64_t near[R][4];
+      // phases after each step and the compensated increments y (the error
+      // terms are recomputed from them only in the rare exact test)
+      float ph_q[R][5], y_q[R][4];
+#pragma unroll
+      for (int r = 0; r < R; ++r) ph_q[r][0] = s[r].phi;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           Slot<FP64>& sl = s[r];
           const auto& p = MULTI ? sl.p : uni.p;
-          const float g = q == 0 ? g0[r] : __builtin_fmaf(p.dG, (float)q, g0[r]);
           const float trig = (q & 1) ? bm[r].s[q >> 1] : bm[r].c[q >> 1];
           if constexpr (MODEL == kUnderExplicit) {
-            step_f32_under(p, g, zs[r][q >> 1], trig, sl.phi, sl.c, sl.v);
+            y_q[r][q] = step_f32_under(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e, sl.v);
           } else if constexpr (MODEL == kUnderSemiImplicit) {
-            step_f32_under_si(p, g, zs[r][q >> 1], trig, sl.phi, sl.c, sl.v);
+            y_q[r][q] =
+                step_f32_under_si(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e, sl.v);
           } else {
-            step_f32_over(p, g, zs[r][q >> 1], trig, sl.phi, sl.c);
+            y_q[r][q] = step_f32_over(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e);
           }
-          ph_q[r][q] = sl.phi;
-          c_q[r][q] = sl.c;
-          near[r][q] = __ballot(sl.phi > p.th_near_rev);
+          ph_q[r][q + 1] = sl.phi;
         }
       }
-      // exact FP64 test only where a lane came near the threshold
+      // one compare per slot and block on the largest phase; the exact FP64
+      // test of each step only where a lane came near the threshold
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const auto& p = MULTI ? s[r].p : uni.p;
         esc[r][0] = esc[r][1] = esc[r][2] = esc[r][3] = 0ull;
-        if (near[r][0] | near[r][1] | near[r][2] | near[r][3]) {
+        const float top = fmaxf(fmaxf(ph_q[r][1], ph_q[r][2]), fmaxf(ph_q[r][3], ph_q[r][4]));
+        if (__ballot(top > p.th_near_rev)) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            esc[r][q] = __ballot(above_f64(ph_q[r][q], c_q[r][q], p.th_rev)) & near[r][q];
+          for (int q = 0; q < 4; ++q) {
+            const float ph = ph_q[r][q + 1];
+            // opaque copy: the error term is recomputed here, not kept live
+            // from the step (which would block the accumulate form there)
+            float y = y_q[r][q];
+            asm volatile("" : "+v"(y));
+            esc[r][q] = __ballot(ph > p.th_near_rev &&
+                                 above_f64(ph, kahan_error(y, ph, ph_q[r][q]), p.th_rev));
+          }
         }
       }
     }
@@ -635,7 +650,7 @@ __global__ __launch_bounds__(kBlockThreads) void init_kernel(SliceArgs a,
   s.kd = 0.0;
   s.phi = 0;
   s.v = 0;
-  s.c = 0.0f;
+  s.e = 0.0f;
   uint32_t set;
   uint64_t idx;
   if (slot < n_assign && map_flat(a, slot, &set, &idx)) {
@@ -735,19 +750,18 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
       }
     } else {
       const BoxMullerF32 bm = box_muller_f32(w);
-      const float g0 = block_g_f32(s.p.gB, s.kd, s.p.gA);
+      const BlockG gk = block_g4(s.p, s.kd, s.p.gA);
       for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
-        const float g = q == 0 ? g0 : __builtin_fmaf(s.p.dG, (float)q, g0);
         const float zs = s.p.sig * bm.radius[q >> 1];
         const float trig = (q & 1) ? bm.s[q >> 1] : bm.c[q >> 1];
         if constexpr (MODEL == kUnderExplicit) {
-          step_f32_under(s.p, g, zs, trig, s.phi, s.c, s.v);
+          step_f32_under(s.p, gk.g[q], zs, trig, s.phi, s.e, s.v);
         } else if constexpr (MODEL == kUnderSemiImplicit) {
-          step_f32_under_si(s.p, g, zs, trig, s.phi, s.c, s.v);
+          step_f32_under_si(s.p, gk.g[q], zs, trig, s.phi, s.e, s.v);
         } else {
-          step_f32_over(s.p, g, zs, trig, s.phi, s.c);
+          step_f32_over(s.p, gk.g[q], zs, trig, s.phi, s.e);
         }
-        out_phi[k0 + q] = 2.0 * kPi * ((double)s.phi - (double)s.c);
+        out_phi[k0 + q] = 2.0 * kPi * ((double)s.phi + (double)s.e);
         out_v[k0 + q] = (double)s.v;
       }
     }

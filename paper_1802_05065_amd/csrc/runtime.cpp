@@ -104,19 +104,21 @@ SetDev derive_set(const fpt_params& p) {
   if (p.model == FPT_UNDERDAMPED) {
     s.gA = p.dt * p.V0 * p.gamma0;     // G_k = h V0 gamma_k
     s.gB = p.dt * p.V0 * s.dgamma;
-    s.kS_f = (float)(p.dt * p.V0);
+    s.nkS_f = (float)(-p.dt * p.V0);
     s.sig_f = (float)(s.sigma * sqrt2ln2);
     s.h_rev_f = (float)(p.dt / twopi);
     s.damp_f = (float)(1.0 - p.dt * p.alpha);
   } else {
     s.gA = p.dt * p.gamma0 / twopi;    // G_k = h gamma_k / 2 pi
     s.gB = p.dt * s.dgamma / twopi;
-    s.kS_f = (float)(p.dt * p.V0 / twopi);
+    s.nkS_f = (float)(-p.dt * p.V0 / twopi);
     s.sig_f = (float)(s.sigma * sqrt2ln2 / twopi);
     s.h_rev_f = 0.0f;
     s.damp_f = 1.0f;
   }
   s.dG_f = (float)s.gB;
+  s.dG2_f = (float)(2.0 * s.gB);
+  s.dG3_f = (float)(3.0 * s.gB);
   s.th_rev = s.th / twopi;
   // at or below th_near_rev_f the compensated phase cannot exceed th_rev:
   // 8 float ulps of margin cover the compensation term and the rounding
@@ -125,7 +127,7 @@ SetDev derive_set(const fpt_params& p) {
   s.th_near_rev_f = tn;
   const double phr0 = s.phi0 / twopi;
   s.phr0_f = (float)phr0;
-  s.c0_f = (float)((double)s.phr0_f - phr0);
+  s.e0_f = (float)(phr0 - (double)s.phr0_f);
   s.v0_f = (float)s.v0;
   s.max_steps = p.max_steps;
   s.jmax = (uint64_t)(p.max_steps - 1) / 4;
