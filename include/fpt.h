@@ -126,7 +126,9 @@ typedef struct fpt_params {
 typedef struct fpt_tuning {
   int32_t schedule;          /* fpt_schedule */
   int32_t replicas_per_lane; /* 1 or 2 (0: autotune) */
-  int32_t waves_per_simd;    /* 1..8 resident waves per SIMD (0: autotune) */
+  int32_t waves_per_simd;    /* 1..8 resident waves per SIMD (0: autotune); capped
+                                at the kernel's occupancy (fpt_plan_stats reports
+                                the value used) */
   int32_t steps_per_launch;  /* multiple of 4 (0: autotune) */
   int32_t use_graph;         /* 1: replay launches through a captured hipGraph */
   int32_t reserved[3];

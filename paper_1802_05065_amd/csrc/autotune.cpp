@@ -97,8 +97,10 @@ void tune_store(const std::string& key, const TuneEntry& e) {
   std::fclose(f);
 }
 
-// Measure one candidate shape: three launches of 256 blocks (1024 steps),
-// the last two timed.  Returns slot-steps/s or a negative value on error.
+// Measure one candidate shape: a warm-up launch of 256 blocks (1024 steps)
+// whose duration sizes the two timed launches to about 8 ms each, so launch
+// overhead and the ramp-up of the persistent grid do not decide the ranking.
+// Returns slot-steps/s (negative if the shape does not fit the workspace).
 static fpt_status trial(Plan& p, char* ws, hipStream_t st, const fpt_tuning& t,
                         double* rate, double* slot_rate) {
   const int R = t.replicas_per_lane;
@@ -120,7 +122,14 @@ static fpt_status trial(Plan& p, char* ws, hipStream_t st, const fpt_tuning& t,
   FPT_TRY(p.ensure_host_resources(3));
   const uint32_t groups = (uint32_t)(lanes / kBlockThreads);
   const bool fp64 = p.precision == FPT_FP64;
+  FPT_HIP(hipEventRecord(p.events[0], st));
   FPT_HIP(launch_slice(fp64, p.model, R, p.multi, a, groups, st));
+  FPT_HIP(hipEventRecord(p.events[1], st));
+  FPT_HIP(hipStreamSynchronize(st));
+  float warm_ms = 0.f;
+  FPT_HIP(hipEventElapsedTime(&warm_ms, p.events[0], p.events[1]));
+  const double scale = warm_ms > 0.f ? 8.0 / (double)warm_ms : 1.0;
+  a.blocks = (int32_t)std::max(256.0, std::min(256.0 * scale, 262144.0));
   FPT_HIP(hipMemcpyAsync(p.h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   FPT_HIP(hipStreamSynchronize(st));
   const unsigned long long before = p.h_ctr->lane_steps;
@@ -136,6 +145,13 @@ static fpt_status trial(Plan& p, char* ws, hipStream_t st, const fpt_tuning& t,
   *rate = ms > 0.f ? steps / (ms * 1e-3) : 0.0;
   *slot_rate = *rate / (double)(lanes * (uint64_t)R);
   return FPT_OK;
+}
+
+// Resident waves per SIMD of the plan's kernel with R replicas per lane
+// (kMaxWavesPerSimd if the runtime cannot say).
+int Plan::resident_waves(int R) const {
+  const int n = slice_resident_groups(precision == FPT_FP64, model, R, multi, mt);
+  return n > 0 ? std::min(n, kMaxWavesPerSimd) : kMaxWavesPerSimd;
 }
 
 fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
@@ -157,11 +173,19 @@ fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
     } else if (total_replicas > 0) {
       std::vector<int> rs = need_r ? std::vector<int>{1, 2}
                                    : std::vector<int>{t.replicas_per_lane};
-      std::vector<int> ws_list = need_w ? std::vector<int>{2, 4, 8}
-                                        : std::vector<int>{t.waves_per_simd};
-      if (t.schedule == FPT_SCHED_ONE_PER_LANE) ws_list = {ws_list.back()};
       double best_rate = -1.0;
       for (int r : rs) {
+        // every resident wave count from 2 up to the kernel's occupancy:
+        // more would leave workgroups of the persistent grid waiting
+        const int occ = resident_waves(r);
+        std::vector<int> ws_list;
+        if (!need_w) {
+          ws_list = {std::min(t.waves_per_simd, occ)};
+        } else if (t.schedule == FPT_SCHED_ONE_PER_LANE) {
+          ws_list = {occ};
+        } else {
+          for (int w = std::min(2, occ); w <= occ; ++w) ws_list.push_back(w);
+        }
         for (int w : ws_list) {
           fpt_tuning c = t;
           c.replicas_per_lane = r;
@@ -187,6 +211,7 @@ fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
   }
   if (t.replicas_per_lane == 0) t.replicas_per_lane = 1;
   if (t.waves_per_simd == 0) t.waves_per_simd = kMaxWavesPerSimd;
+  t.waves_per_simd = std::min(t.waves_per_simd, resident_waves(t.replicas_per_lane));
   if (need_s) {
     uint64_t s = 16384;
     if (have_rate && best.per_slot_steps_per_s > 0)

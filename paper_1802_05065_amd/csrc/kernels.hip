@@ -471,6 +471,10 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
 
     // ---- 4 Euler steps per slot
     uint64_t esc[R][4];
+    // the generator key re-derived each block: its 20 round keys are then
+    // recomputed on the scalar unit instead of occupying scalar registers
+    uint32_t key0 = uni.k0, key1 = uni.k1;
+    asm volatile("" : "+s"(key0), "+s"(key1));
     if constexpr (FP64) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -478,7 +482,7 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
         const auto& p = MULTI ? sl.p : uni.p;
         const Words w = block_words<MT>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
                                         (amask[r] & lane_bit) != 0, mc[r], sl,
-                                        MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
+                                        MULTI ? sl.k0 : key0, MULTI ? sl.k1 : key1);
         double z[4];
         normals_f64(w, z);
 #pragma unroll
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
         const auto& p = MULTI ? sl.p : uni.p;
         const Words w = block_words<MT>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
                                         (amask[r] & lane_bit) != 0, mc[r], sl,
-                                        MULTI ? sl.k0 : uni.k0, MULTI ? sl.k1 : uni.k1);
+                                        MULTI ? sl.k0 : key0, MULTI ? sl.k1 : key1);
         bm[r] = box_muller_f32(w);
         gk[r] = block_g4(p, sl.kd, MULTI ? p.gA : gA_uni);
         // all four bias terms exist before the first step, so every step can
@@ -773,49 +777,56 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
 // ---------------------------------------------------------------------------
 // Host-side launchers
 
-template <bool FP64, int MODEL, int R, bool MULTI, bool MT = false>
-static hipError_t launch_slice_t(const SliceArgs& a, uint32_t n_groups,
-                                 hipStream_t st) {
-  hipLaunchKernelGGL((slice_kernel<FP64, MODEL, R, MULTI, MT>), dim3(n_groups),
-                     dim3(kBlockThreads), 0, st, a);
-  return hipGetLastError();
-}
-
+// The slice kernel instance for (precision, kind, R, multi, MT).
 template <bool FP64, int MODEL, int R>
-static hipError_t launch_slice_m(bool multi, const SliceArgs& a, uint32_t n_groups,
-                                 hipStream_t st) {
-  return multi ? launch_slice_t<FP64, MODEL, R, true>(a, n_groups, st)
-               : launch_slice_t<FP64, MODEL, R, false>(a, n_groups, st);
-}
-
-template <bool FP64, int MODEL>
-static hipError_t launch_slice_r(int R, bool multi, const SliceArgs& a,
-                                 uint32_t n_groups, hipStream_t st) {
-  if (a.st_mt) {
-    if (R != 1 || multi) return hipErrorInvalidValue;
-    return launch_slice_t<FP64, MODEL, 1, false, true>(a, n_groups, st);
+static const void* slice_ptr_m(bool multi, bool mt) {
+  if constexpr (R == 1) {
+    if (mt) return multi ? nullptr : (const void*)&slice_kernel<FP64, MODEL, 1, false, true>;
+  } else {
+    if (mt) return nullptr;
   }
-  return R == 2 ? launch_slice_m<FP64, MODEL, 2>(multi, a, n_groups, st)
-                : launch_slice_m<FP64, MODEL, 1>(multi, a, n_groups, st);
+  return multi ? (const void*)&slice_kernel<FP64, MODEL, R, true, false>
+               : (const void*)&slice_kernel<FP64, MODEL, R, false, false>;
 }
 
 template <bool FP64>
-static hipError_t launch_slice_k(int kind, int R, bool multi, const SliceArgs& a,
-                                 uint32_t n_groups, hipStream_t st) {
+static const void* slice_ptr_k(int kind, int R, bool multi, bool mt) {
   switch (kind) {
     case kOver:
-      return launch_slice_r<FP64, kOver>(R, multi, a, n_groups, st);
+      return R == 2 ? slice_ptr_m<FP64, kOver, 2>(multi, mt)
+                    : slice_ptr_m<FP64, kOver, 1>(multi, mt);
     case kUnderSemiImplicit:
-      return launch_slice_r<FP64, kUnderSemiImplicit>(R, multi, a, n_groups, st);
+      return R == 2 ? slice_ptr_m<FP64, kUnderSemiImplicit, 2>(multi, mt)
+                    : slice_ptr_m<FP64, kUnderSemiImplicit, 1>(multi, mt);
     default:
-      return launch_slice_r<FP64, kUnderExplicit>(R, multi, a, n_groups, st);
+      return R == 2 ? slice_ptr_m<FP64, kUnderExplicit, 2>(multi, mt)
+                    : slice_ptr_m<FP64, kUnderExplicit, 1>(multi, mt);
   }
+}
+
+static const void* slice_ptr(bool fp64, int kind, int R, bool multi, bool mt) {
+  if (R != 1 && R != 2) return nullptr;
+  return fp64 ? slice_ptr_k<true>(kind, R, multi, mt) : slice_ptr_k<false>(kind, R, multi, mt);
 }
 
 hipError_t launch_slice(bool fp64, int kind, int R, bool multi,
                         const SliceArgs& a, uint32_t n_groups, hipStream_t st) {
-  return fp64 ? launch_slice_k<true>(kind, R, multi, a, n_groups, st)
-              : launch_slice_k<false>(kind, R, multi, a, n_groups, st);
+  const void* f = slice_ptr(fp64, kind, R, multi, a.st_mt != nullptr);
+  if (!f) return hipErrorInvalidValue;
+  SliceArgs args = a;
+  void* params[] = {&args};
+  return hipLaunchKernel(f, dim3(n_groups), dim3(kBlockThreads), params, 0, st);
+}
+
+int slice_resident_groups(bool fp64, int kind, int R, bool multi, bool mt) {
+  const void* f = slice_ptr(fp64, kind, R, multi, mt);
+  int n = 0;
+  if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlockThreads, 0) !=
+                hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
 }
 
 hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,

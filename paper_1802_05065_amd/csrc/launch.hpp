@@ -13,6 +13,9 @@ namespace fpt {
 // a.st_mt non-null selects the MT19937 kernels (R = 1, single set only).
 hipError_t launch_slice(bool fp64, int kind, int R, bool multi,
                         const SliceArgs& a, uint32_t n_groups, hipStream_t st);
+// Workgroups of the slice kernel instance that fit on one CU at once (one
+// 256-thread workgroup is one wave per SIMD), 0 if unknown.
+int slice_resident_groups(bool fp64, int kind, int R, bool multi, bool mt);
 hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,
                        uint64_t n_assign, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n,

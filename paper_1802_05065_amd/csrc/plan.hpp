@@ -52,6 +52,7 @@ struct Plan {
   fpt_status layout();
   SliceArgs slice_args(char* ws, uint64_t* hist, uint64_t n_lanes) const;
   uint64_t lanes_for(const fpt_tuning& t) const;
+  int resident_waves(int R) const;
   uint64_t launch_bound(uint64_t n_slots, int blocks) const;
   fpt_status ensure_host_resources(size_t n_events);
   fpt_status upload_sets(char* ws, const std::vector<SetDev>& table, hipStream_t st);

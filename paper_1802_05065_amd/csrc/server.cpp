@@ -172,6 +172,12 @@ fpt_status Server::setup() {
   }
   if (!tuning.replicas_per_lane) tuning.replicas_per_lane = 1;
   if (!tuning.waves_per_simd) tuning.waves_per_simd = kMaxWavesPerSimd;
+  {
+    // no more persistent workgroups than fit on the chip at once
+    const int occ = slice_resident_groups(precision == FPT_FP64, model,
+                                          tuning.replicas_per_lane, true, false);
+    if (occ > 0) tuning.waves_per_simd = std::min(tuning.waves_per_simd, occ);
+  }
   if (!tuning.steps_per_launch) tuning.steps_per_launch = 8192;
   tuning.schedule = FPT_SCHED_REFILL;
   n_lanes = (uint64_t)di.cus * 4 * (uint64_t)tuning.waves_per_simd * kWave;
