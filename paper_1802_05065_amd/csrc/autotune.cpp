@@ -5,7 +5,8 @@
 // lane R (register-level ILP), resident waves per SIMD W (occupancy) and steps
 // per launch S.  Candidates run a few short launches on the plan's own
 // parameter sets (outputs discarded, counters reset afterwards); the shape
-// with the highest measured slot-steps/s wins.  S is then sized from the
+// with the highest measured slot-steps/s, discounted by the fill of the last
+// round of replicas when they outnumber the slots, wins.  S is then sized from the
 // winner's steps/s per resident slot so that one launch lasts about
 // FPT_LAUNCH_MS milliseconds (default 40).  Winners are
 // cached in memory and in a JSON-lines file (FPT_TUNE_CACHE, default
@@ -13,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -192,8 +194,15 @@ fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
           c.waves_per_simd = w;
           double rate = 0.0, slot_rate = 0.0;
           FPT_TRY(trial(*this, ws, st, c, &rate, &slot_rate));
-          if (rate > best_rate) {
-            best_rate = rate;
+          // replicas of similar lifetime run in rounds of one per slot; a
+          // last round that fills only part of the slots idles the rest, so
+          // the shape is ranked by its rate times that round's fill
+          const double slots = (double)(lanes_for(c) * (uint64_t)r);
+          const double rounds = slots > 0 ? (double)total_flat / slots : 1.0;
+          const double fill = rounds <= 1.0 ? 1.0 : rounds / std::ceil(rounds);
+          const double score = rate * fill;
+          if (score > best_rate) {
+            best_rate = score;
             best.replicas_per_lane = r;
             best.waves_per_simd = w;
             best.slot_steps_per_s = rate;

@@ -44,6 +44,30 @@ __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1,
   return Words{c0, c1, c2, c3};
 }
 
+// The same with a wavefront-uniform key: each round key is formed on the
+// scalar unit just before its round (the opaque copy stops the compiler from
+// hoisting all 20 into scalar registers at once, which would cost the
+// integrator a resident wave).
+__device__ __forceinline__ Words philox4x32_10_uniform_key(uint32_t c0, uint32_t c1,
+                                                           uint32_t c2, uint32_t c3,
+                                                           uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c3, k1, 0x96);
+    c1 = (uint32_t)pb;
+    c3 = (uint32_t)pa;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Words{c0, c1, c2, c3};
+}
+
 // Words of block j of replica idx: counter (j lo, j hi, idx lo, idx hi),
 // key (seed lo, seed hi).
 __device__ __forceinline__ Words replica_words(uint64_t seed, uint64_t idx,
@@ -246,6 +270,22 @@ __device__ __forceinline__ BlockG block_g4(const ParF32& p, double k1, double gA
   b.g[1] = b.g[0] + p.dG;
   b.g[2] = b.g[0] + p.dG2;
   b.g[3] = b.g[0] + p.dG3;
+  return b;
+}
+
+// Histogram bin of escape step k in [1, k_hist]: floor((k-1) n_bins / k_hist),
+// exactly, with scale = n_bins / k_hist.  The FP64 quotient is within 1e-12
+// of the true one (k-1 < 2^53, quotient < 2^12), so one integer correction
+// step either way makes it exact; a software 64-bit division here would set
+// the integrator's register count.
+__host__ __device__ __forceinline__ uint32_t hist_bin_of(int64_t k, uint32_t n_bins,
+                                                         int64_t k_hist, double scale) {
+  const uint64_t num = (uint64_t)(k - 1) * (uint64_t)n_bins;
+  const uint64_t kh = (uint64_t)k_hist;
+  const double est = (double)(k - 1) * scale;
+  uint32_t b = est < (double)(n_bins - 1) ? (uint32_t)est : n_bins - 1;
+  if (b > 0 && (uint64_t)b * kh > num) --b;
+  if ((uint64_t)(b + 1) * kh <= num) ++b;
   return b;
 }
 

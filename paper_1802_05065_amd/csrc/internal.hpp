@@ -44,6 +44,7 @@ struct alignas(16) SetDev {
   int64_t max_steps;    // klim
   uint64_t jmax;        // block of the last allowed step: (max_steps - 1) / 4
   int64_t k_hist;       // histogram covers steps [1, k_hist]
+  double hist_scale;    // n_bins / k_hist (estimate of the bin, corrected exactly)
   uint64_t seed;
   uint64_t n_replicas;
   int64_t* out_steps;   // device, may be null

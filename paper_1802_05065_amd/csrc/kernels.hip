@@ -181,20 +181,28 @@ struct LdsTables {
   unsigned long long m_val[kMomSlots][6];  // esc, cens, over, sum_k, k2 lo, hi
 };
 
+// Table slot of a key, (set << 12 | bin) or set: shifts and XORs only, so no
+// multiplier constant is held in a scalar register for the whole kernel
+// (the integrator's resident-wave count depends on those registers).
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
-  return (x * 2654435761u) >> 16;
+  return x ^ (x >> 10) ^ (x >> 20);
 }
 
 // Per-set output description needed when a replica finishes.
 struct SetOut {
   int64_t* out_steps;
   int64_t k_hist;
+  double hist_scale;
   uint64_t hist_off;
   uint32_t n_bins;
 };
 
 __device__ __forceinline__ SetOut set_out(const SetDev& s) {
-  return SetOut{s.out_steps, s.k_hist, s.hist_off, s.n_bins};
+  return SetOut{s.out_steps, s.k_hist, s.hist_scale, s.hist_off, s.n_bins};
+}
+
+__device__ __forceinline__ uint32_t hist_bin(int64_t k, const SetOut& so) {
+  return hist_bin_of(k, so.n_bins, so.k_hist, so.hist_scale);
 }
 
 __device__ void hist_add(LdsTables& t, const SliceArgs& a, uint32_t key,
@@ -252,16 +260,15 @@ __device__ void mom_add(LdsTables& t, const SliceArgs& a, uint32_t set,
 // have finished with step k (k = -1: censored).
 __device__ void record_finished(LdsTables& t, const SliceArgs& a, bool fin,
                                 uint32_t set, uint64_t idx, int64_t k) {
-  SetOut so{nullptr, 1, 0, 1};
+  SetOut so{nullptr, 1, 1.0, 0, 1};
   uint32_t key = kEmpty;
   bool in_hist = false;
   if (fin) {
     so = set_out(a.sets[set]);
     if (so.out_steps) so.out_steps[idx] = k;
     if (k > 0 && k <= so.k_hist) {
-      const uint64_t bin =
-          (uint64_t)((k - 1) * (int64_t)so.n_bins) / (uint64_t)so.k_hist;
-      key = (set << kBinBits) | (uint32_t)bin;
+      const uint32_t bin = hist_bin(k, so);
+      key = (set << kBinBits) | bin;
       in_hist = true;
     }
     mom_add(t, a, set, k, k > so.k_hist);
@@ -354,7 +361,7 @@ __device__ __forceinline__ uint32_t blocks_to_cap(const Slot<FP64>& sl, uint64_t
 // The 4 words of a slot's next block: Philox keyed by (block, replica), or
 // the next 4 outputs of the replica's MT19937 (active lanes only: a free
 // slot's state is re-seeded when it takes a replica).
-template <bool MT, bool FP64>
+template <bool MT, bool UNIFORM_KEY, bool FP64>
 __device__ __forceinline__ Words block_words(const SliceArgs& a, uint64_t n_slots,
                                              uint64_t slot, bool active, MtCarry& mc,
                                              const Slot<FP64>& sl, uint32_t k0,
@@ -363,6 +370,9 @@ __device__ __forceinline__ Words block_words(const SliceArgs& a, uint64_t n_slot
     Words w{0u, 0u, 0u, 0u};
     if (active) w = mt_block(a.st_mt, n_slots, slot, mc);
     return w;
+  } else if constexpr (UNIFORM_KEY) {
+    return philox4x32_10_uniform_key((uint32_t)sl.j, (uint32_t)(sl.j >> 32),
+                                     (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32), k0, k1);
   } else {
     return philox4x32_10((uint32_t)sl.j, (uint32_t)(sl.j >> 32), (uint32_t)sl.idx,
                          (uint32_t)(sl.idx >> 32), k0, k1);
@@ -471,16 +481,13 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
 
     // ---- 4 Euler steps per slot
     uint64_t esc[R][4];
-    // the generator key re-derived each block: its 20 round keys are then
-    // recomputed on the scalar unit instead of occupying scalar registers
-    uint32_t key0 = uni.k0, key1 = uni.k1;
-    asm volatile("" : "+s"(key0), "+s"(key1));
+    const uint32_t key0 = uni.k0, key1 = uni.k1;
     if constexpr (FP64) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         Slot<FP64>& sl = s[r];
         const auto& p = MULTI ? sl.p : uni.p;
-        const Words w = block_words<MT>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
+        const Words w = block_words<MT, !MULTI>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
                                         (amask[r] & lane_bit) != 0, mc[r], sl,
                                         MULTI ? sl.k0 : key0, MULTI ? sl.k1 : key1);
         double z[4];
@@ -508,7 +515,7 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
       for (int r = 0; r < R; ++r) {
         Slot<FP64>& sl = s[r];
         const auto& p = MULTI ? sl.p : uni.p;
-        const Words w = block_words<MT>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
+        const Words w = block_words<MT, !MULTI>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
                                         (amask[r] & lane_bit) != 0, mc[r], sl,
                                         MULTI ? sl.k0 : key0, MULTI ? sl.k1 : key1);
         bm[r] = box_muller_f32(w);

@@ -132,6 +132,7 @@ SetDev derive_set(const fpt_params& p) {
   s.max_steps = p.max_steps;
   s.jmax = (uint64_t)(p.max_steps - 1) / 4;
   s.k_hist = p.hist_k_max > 0 ? p.hist_k_max : p.max_steps;
+  s.hist_scale = (double)p.n_bins / (double)s.k_hist;
   s.seed = p.seed;
   s.n_replicas = (uint64_t)p.n_replicas;
   s.out_steps = nullptr;
