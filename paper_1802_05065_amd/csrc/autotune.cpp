@@ -8,7 +8,8 @@
 // with the highest measured slot-steps/s, discounted by the fill of the last
 // round of replicas when they outnumber the slots, wins.  S is then sized from the
 // winner's steps/s per resident slot so that one launch lasts about
-// FPT_LAUNCH_MS milliseconds (default 40).  Winners are
+// FPT_LAUNCH_MS milliseconds (default 40); FPT_TUNE_VERBOSE=1 prints each
+// trial.  Winners are
 // cached in memory and in a JSON-lines file (FPT_TUNE_CACHE, default
 // $HOME/.cache/fpt_tune.jsonl), one object per key.
 #include <hip/hip_runtime.h>
@@ -67,6 +68,12 @@ double launch_ms_target() {
   return 40.0;
 }
 }  // namespace
+
+// FPT_TUNE_VERBOSE=1 prints every trial to stderr.
+static bool tune_verbose() {
+  const char* v = std::getenv("FPT_TUNE_VERBOSE");
+  return v && v[0] == '1';
+}
 
 std::string tune_key(const std::string& arch, int precision, int model, int schedule,
                      bool multi) {
@@ -201,6 +208,11 @@ fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
           const double rounds = slots > 0 ? (double)total_flat / slots : 1.0;
           const double fill = rounds <= 1.0 ? 1.0 : rounds / std::ceil(rounds);
           const double score = rate * fill;
+          if (tune_verbose())
+            std::fprintf(stderr,
+                         "[fpt tune] R=%d W=%d lanes=%llu rate=%.4e slot-steps/s fill=%.3f "
+                         "score=%.4e\n",
+                         r, w, (unsigned long long)lanes_for(c), rate, fill, score);
           if (score > best_rate) {
             best_rate = score;
             best.replicas_per_lane = r;
