@@ -42,6 +42,42 @@ OPS_FP32C = (40 + 8 + 10 + 5 + 36 + 2) / 4.0
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
 
 
+# Instructions per 4-step block of one replica as the FP32C underdamped kernel
+# compiles them for gfx950 (its hot loop's disassembly), by issue class; each
+# class is priced at the rate profiles/isa_rates_gfx950.txt measured for it.
+FP32C_BLOCK_MIX = {
+    "mad_u64_u32_s0": 20,  # Philox products
+    "bitop3_b32_s": 20,    # Philox three-input XORs
+    "sin_f32": 6, "cos_f32": 2, "log_f32": 2, "sqrt_f32": 2,
+    "fmac_f32_s": 13,      # Kahan increment, noise, force, damping
+    "add_f32": 9,          # Kahan sums, bias offsets, near-threshold max and compare
+    "sub_f32": 7,          # Kahan error terms
+    "mul_f32": 2, "fmamk_f32": 2,
+    "cvt_f32_u32": 3,      # uniforms, bias to FP32
+    "fma_f32_s": 3,        # other VOP3: angle bit-alignment, max3
+    "fma_f64": 1, "add_f64": 1,  # bias G_k and step count in FP64
+    "add_u32": 2,          # block index
+}
+
+
+def mix_attainable(mix=FP32C_BLOCK_MIX):
+    """Replica-steps/s the instruction mix can issue at the measured per-class
+    rates (None without the rate table)."""
+    path = os.path.join(ROOT, "profiles", "isa_rates_gfx950.txt")
+    rates = {}
+    try:
+        for line in open(path):
+            f = line.split()
+            if len(f) == 4 and f[1] == "1":
+                rates[f[0]] = float(f[2]) * 1e12
+    except OSError:
+        return None
+    if not all(k in rates for k in mix):
+        return None
+    block_s = sum(n / rates[k] for k, n in mix.items())
+    return 4.0 / block_s
+
+
 def counter_traffic(slots: int):
     """HBM bytes per launch of the FP32C slice kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel sources
@@ -433,6 +469,9 @@ def main():
                 * st["tuning"]["waves_per_simd"] * st["tuning"]["replicas_per_lane"]),
             "kernel": "slice_kernel<fp32c, underdamped>",
             "ops_per_replica_step": OPS_FP32C,
+            "mix_attainable_replica_steps_per_s": mix_attainable(),
+            "frac_of_mix_attainable": (st["replica_steps"] / kernel_s / mix_attainable()
+                                       if kernel_s > 0 and mix_attainable() else None),
             "avg_launch_ms": st["kernel_ms"] / launches, "launches": st["n_launches"]}
 
     latency = None
