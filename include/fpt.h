@@ -131,7 +131,12 @@ typedef struct fpt_tuning {
                                 the value used) */
   int32_t steps_per_launch;  /* multiple of 4 (0: autotune) */
   int32_t use_graph;         /* 1: replay launches through a captured hipGraph */
-  int32_t reserved[3];
+  int32_t no_compaction;     /* 1: keep the launch width to the end.  Otherwise a
+                                refill plan (Philox) whose queue is drained and
+                                whose active replicas fill at most half the slots
+                                moves them to a dense prefix and narrows later
+                                launches; results do not change */
+  int32_t reserved[2];
 } fpt_tuning;
 
 /* Per-set results.  Moments are over escaped replicas; times in units of t. */
@@ -149,6 +154,7 @@ typedef struct fpt_run_stats {
   double kernel_ms;           /* sum of their durations (HIP events) */
   double wall_ms;             /* fpt_simulate entry to last launch done */
   fpt_tuning tuning;          /* tuning actually used */
+  int64_t n_compactions;      /* tail compactions of the last simulate */
 } fpt_run_stats;
 
 typedef struct fpt_plan_s* fpt_plan_t;

@@ -82,7 +82,8 @@ class FptTuning(ctypes.Structure):
         ("waves_per_simd", ctypes.c_int32),
         ("steps_per_launch", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("no_compaction", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -107,6 +108,7 @@ class FptRunStats(ctypes.Structure):
         ("kernel_ms", ctypes.c_double),
         ("wall_ms", ctypes.c_double),
         ("tuning", FptTuning),
+        ("n_compactions", ctypes.c_int64),
     ]
 
 
@@ -201,7 +203,7 @@ def make_tuning(t: Optional[Dict]) -> Optional[FptTuning]:
         return None
     return FptTuning(int(t.get("schedule", 0)), int(t.get("replicas_per_lane", 0)),
                      int(t.get("waves_per_simd", 0)), int(t.get("steps_per_launch", 0)),
-                     int(t.get("use_graph", 0)))
+                     int(t.get("use_graph", 0)), int(t.get("no_compaction", 0)))
 
 
 def moments_dict(m: FptMoments) -> Dict:
@@ -250,9 +252,11 @@ def fpt_plan_stats(plan: int) -> Dict:
     t = s.tuning
     return dict(replica_steps=s.replica_steps, lane_steps=s.lane_steps,
                 n_launches=s.n_launches, kernel_ms=s.kernel_ms, wall_ms=s.wall_ms,
+                n_compactions=s.n_compactions,
                 tuning=dict(schedule=t.schedule, replicas_per_lane=t.replicas_per_lane,
                             waves_per_simd=t.waves_per_simd,
-                            steps_per_launch=t.steps_per_launch, use_graph=t.use_graph))
+                            steps_per_launch=t.steps_per_launch, use_graph=t.use_graph,
+                            no_compaction=t.no_compaction))
 
 
 def fpt_plan_destroy(plan: int) -> None:

@@ -38,8 +38,9 @@ def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
         cmd = [HIPCC, *COMMON, *DEVICE, "-c", path, "-o", obj]
-    else:
-        cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
+    else:  # host code of the runtime: no device pass
+        cmd = [HIPCC, *COMMON, "--offload-arch=" + ARCH, "--cuda-host-only", "-c", path,
+               "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -70,7 +70,8 @@ struct alignas(16) Counters {
   unsigned long long cursor;      // next flat replica index to hand out
   unsigned long long done;        // replicas finished (escaped or censored)
   unsigned long long lane_steps;  // lane-steps issued, idle lanes included
-  unsigned long long pad[5];
+  unsigned long long compact;     // active slots found by a compaction pass
+  unsigned long long pad[4];
 };
 
 // Arguments of one integrator launch.

@@ -672,6 +672,53 @@ __global__ __launch_bounds__(kBlockThreads) void init_kernel(SliceArgs a,
   store_slot(a, slot, s);
 }
 
+// ---------------------------------------------------------------------------
+// Tail compaction: once no undrawn replica is left, the active slots' state
+// moves to a dense prefix of another state buffer, so later launches need
+// fewer workgroups and no wave runs mostly idle lanes.  Which slot runs a
+// replica does not change its results.
+
+// Wavefront-aggregated claim of consecutive positions for the flagged lanes.
+__device__ __forceinline__ uint64_t claim_positions(unsigned long long* counter,
+                                                    bool flag) {
+  const uint64_t mask = __ballot(flag);
+  if (mask == 0) return 0;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == (uint32_t)leader)
+    base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+  base = read_lane_u64(base, leader);
+  return base + rank_in(mask);
+}
+
+__global__ __launch_bounds__(kBlockThreads) void compact_count_kernel(SliceArgs a,
+                                                                      uint64_t n_slots) {
+  const uint64_t slot = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  const bool act = slot < n_slots && a.st_set[slot] != kInactive;
+  (void)claim_positions(&a.ctr->compact, act);
+}
+
+// dst's set array must already mark every slot inactive.
+__global__ __launch_bounds__(kBlockThreads) void compact_move_kernel(SliceArgs src,
+                                                                     SliceArgs dst,
+                                                                     uint64_t n_slots) {
+  const uint64_t slot = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  const uint32_t set = slot < n_slots ? src.st_set[slot] : kInactive;
+  const bool act = set != kInactive;
+  const uint64_t pos = claim_positions(&src.ctr->compact, act);
+  if (!act) return;
+  dst.st_set[pos] = set;
+  dst.st_idx[pos] = src.st_idx[slot];
+  dst.st_j[pos] = src.st_j[slot];
+  dst.st_phi[pos] = src.st_phi[slot];
+  dst.st_v[pos] = src.st_v[slot];
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t value) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
 __global__ void fill_u64_kernel(unsigned long long* p, uint64_t n,
                                 unsigned long long value) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -847,6 +894,29 @@ hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,
     hipLaunchKernelGGL(init_kernel<false>, dim3(groups), dim3(kBlockThreads), 0, st,
                        a, n_slots, n_assign);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_count(const SliceArgs& a, uint64_t n_slots, hipStream_t st) {
+  if (n_slots == 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_count_kernel,
+                     dim3((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads)),
+                     dim3(kBlockThreads), 0, st, a, n_slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_move(const SliceArgs& src, const SliceArgs& dst, uint64_t n_slots,
+                               uint64_t n_dst_slots, hipStream_t st) {
+  if (n_dst_slots > 0) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((uint32_t)((n_dst_slots + 255) / 256)), dim3(256),
+                       0, st, dst.st_set, n_dst_slots, kInactive);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (n_slots == 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_move_kernel,
+                     dim3((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads)),
+                     dim3(kBlockThreads), 0, st, src, dst, n_slots);
   return hipGetLastError();
 }
 

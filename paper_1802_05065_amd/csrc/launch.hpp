@@ -18,6 +18,13 @@ hipError_t launch_slice(bool fp64, int kind, int R, bool multi,
 int slice_resident_groups(bool fp64, int kind, int R, bool multi, bool mt);
 hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,
                        uint64_t n_assign, hipStream_t st);
+// Tail compaction (no MT19937 state): count the active slots of `a` into
+// a.ctr->compact, then move them to positions [0, count) of `dst` (whose
+// first n_dst_slots slots are first marked inactive); the counter must be
+// zero before each pass.
+hipError_t launch_compact_count(const SliceArgs& a, uint64_t n_slots, hipStream_t st);
+hipError_t launch_compact_move(const SliceArgs& src, const SliceArgs& dst, uint64_t n_slots,
+                               uint64_t n_dst_slots, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n,
                            unsigned long long value, hipStream_t st);
 hipError_t launch_rng_words(uint64_t seed, uint64_t replica0, uint64_t n_rep,

@@ -32,6 +32,9 @@ struct Plan {
   uint64_t off_sets = 0, off_chunks = 0, off_ctr = 0, off_mom = 0, off_hist = 0;
   uint64_t off_st_phi = 0, off_st_v = 0, off_st_j = 0, off_st_idx = 0, off_st_set = 0;
   uint64_t off_st_mt = 0;
+  // second lane-state buffer for tail compaction (refill plans without MT)
+  uint64_t off_alt_phi = 0, off_alt_v = 0, off_alt_j = 0, off_alt_idx = 0, off_alt_set = 0;
+  bool has_alt = false;
   uint64_t ws_bytes = 0;
 
   // last run
@@ -50,7 +53,9 @@ struct Plan {
 
   ~Plan();
   fpt_status layout();
-  SliceArgs slice_args(char* ws, uint64_t* hist, uint64_t n_lanes) const;
+  SliceArgs slice_args(char* ws, uint64_t* hist, uint64_t n_lanes, int buf = 0) const;
+  fpt_status maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes, int R,
+                           hipStream_t st, bool* compacted);
   uint64_t lanes_for(const fpt_tuning& t) const;
   int resident_waves(int R) const;
   uint64_t launch_bound(uint64_t n_slots, int blocks) const;

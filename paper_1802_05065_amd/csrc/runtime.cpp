@@ -203,11 +203,24 @@ fpt_status Plan::layout() {
   off = align256(off + 4 * slots);
   off_st_mt = off;
   if (mt) off = align256(off + sizeof(uint4) * kMtGroupsPerSlot * slots);
+  has_alt = !mt && tuning_req.schedule == FPT_SCHED_REFILL;
+  if (has_alt) {
+    off_alt_phi = off;
+    off = align256(off + 8 * slots);
+    off_alt_v = off;
+    off = align256(off + 8 * slots);
+    off_alt_j = off;
+    off = align256(off + 8 * slots);
+    off_alt_idx = off;
+    off = align256(off + 8 * slots);
+    off_alt_set = off;
+    off = align256(off + 4 * slots);
+  }
   ws_bytes = off;
   return FPT_OK;
 }
 
-SliceArgs Plan::slice_args(char* ws, uint64_t* hist_dev, uint64_t n_lanes_) const {
+SliceArgs Plan::slice_args(char* ws, uint64_t* hist_dev, uint64_t n_lanes_, int buf) const {
   SliceArgs a;
   std::memset(&a, 0, sizeof(a));
   a.sets = reinterpret_cast<const SetDev*>(ws + off_sets);
@@ -220,6 +233,13 @@ SliceArgs Plan::slice_args(char* ws, uint64_t* hist_dev, uint64_t n_lanes_) cons
   a.st_j = reinterpret_cast<unsigned long long*>(ws + off_st_j);
   a.st_idx = reinterpret_cast<unsigned long long*>(ws + off_st_idx);
   a.st_set = reinterpret_cast<uint32_t*>(ws + off_st_set);
+  if (buf == 1 && has_alt) {
+    a.st_phi = reinterpret_cast<unsigned long long*>(ws + off_alt_phi);
+    a.st_v = reinterpret_cast<unsigned long long*>(ws + off_alt_v);
+    a.st_j = reinterpret_cast<unsigned long long*>(ws + off_alt_j);
+    a.st_idx = reinterpret_cast<unsigned long long*>(ws + off_alt_idx);
+    a.st_set = reinterpret_cast<uint32_t*>(ws + off_alt_set);
+  }
   a.st_mt = mt ? reinterpret_cast<uint4*>(ws + off_st_mt) : nullptr;
   a.n_lanes = n_lanes_;
   a.hist = reinterpret_cast<unsigned long long*>(hist_dev);
@@ -297,6 +317,41 @@ uint64_t Plan::launch_bound(uint64_t n_slots, int blocks) const {
   return 2 * (spread + longest / (uint64_t)blocks + 1) + 16;
 }
 
+// Tail compaction between launches (the counters in h_ctr are current): when
+// no undrawn replica is left and the active ones fill at most half of the
+// slots, count them, and if the launch can narrow by a quarter or more, move
+// their state to a dense prefix of the other state buffer.
+fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes, int R,
+                               hipStream_t st, bool* compacted) {
+  *compacted = false;
+  if (!has_alt || tuning.no_compaction || !a.refill) return FPT_OK;
+  if (h_ctr->cursor < total_flat || lanes <= (uint64_t)kBlockThreads) return FPT_OK;
+  const uint64_t slots = lanes * (uint64_t)R;
+  const uint64_t done = (uint64_t)h_ctr->done;
+  const uint64_t active_bound = total_flat - std::min<uint64_t>(done, total_flat);
+  if (active_bound * 2 > slots) return FPT_OK;
+  FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, st));
+  FPT_HIP(launch_compact_count(a, slots, st));
+  FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  FPT_HIP(hipStreamSynchronize(st));
+  const uint64_t active = h_ctr->compact;
+  const uint64_t new_lanes = std::max<uint64_t>(
+      kBlockThreads, round_up((active + (uint64_t)R - 1) / (uint64_t)R, kBlockThreads));
+  if (new_lanes * 4 > lanes * 3) return FPT_OK;
+  SliceArgs dst = slice_args(ws, reinterpret_cast<uint64_t*>(a.hist), new_lanes, 1 - buf);
+  dst.blocks = a.blocks;
+  dst.refill = a.refill;
+  dst.clamp = a.clamp;
+  FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, st));
+  FPT_HIP(launch_compact_move(a, dst, slots, new_lanes * (uint64_t)R, st));
+  a = dst;
+  buf = 1 - buf;
+  lanes = new_lanes;
+  ++stats.n_compactions;
+  *compacted = true;
+  return FPT_OK;
+}
+
 fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
                           uint64_t* out_hist, hipStream_t st) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -329,7 +384,8 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
   a.refill = refill ? 1 : 0;
   FPT_TRY(reset_run(a, n_lanes, R, refill, st));
 
-  const uint32_t groups = (uint32_t)(n_lanes / kBlockThreads);
+  uint64_t lanes = n_lanes;  // narrows at each tail compaction
+  int buf = 0;
   const bool fp64 = precision == FPT_FP64;
   const uint64_t bound = launch_bound(n_slots, blocks);
   stats = fpt_run_stats{};
@@ -342,37 +398,43 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
   size_t ev_used = 0;
 
   if (tuning.use_graph && !finished) {
-    // A fixed group of launches plus the status copy is captured once on a
+    // A fixed group of launches plus the status copy is captured on a
     // plan-owned stream (the legacy NULL stream cannot be captured) and
     // replayed; events order it after earlier work on `st` and order later
-    // work on `st` after it.
+    // work on `st` after it.  A tail compaction changes the launch width,
+    // so the graph is captured again after one.
     group = 8;
     FPT_TRY(ensure_host_resources(4));
     if (!graph_stream) FPT_HIP(hipStreamCreateWithFlags(&graph_stream, hipStreamNonBlocking));
     FPT_HIP(hipEventRecord(events[2], st));
     FPT_HIP(hipStreamWaitEvent(graph_stream, events[2], 0));
-    if (graph_exec) {
-      (void)hipGraphExecDestroy(graph_exec);
-      graph_exec = nullptr;
-    }
-    hipGraph_t g = nullptr;
-    FPT_HIP(hipStreamBeginCapture(graph_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t cap_err = hipSuccess;
-    for (int i = 0; i < group && cap_err == hipSuccess; ++i)
-      cap_err = launch_slice(fp64, model, R, multi, a, groups, graph_stream);
-    if (cap_err == hipSuccess)
-      cap_err = hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
-                               graph_stream);
-    hipError_t end_err = hipStreamEndCapture(graph_stream, &g);
-    if (cap_err != hipSuccess || end_err != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return fail(FPT_E_DEVICE, "graph capture failed: %s",
-                  hipGetErrorString(cap_err != hipSuccess ? cap_err : end_err));
-    }
-    hipError_t inst = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (inst != hipSuccess)
-      return fail(FPT_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(inst));
+    auto capture = [&]() -> fpt_status {
+      if (graph_exec) {
+        (void)hipGraphExecDestroy(graph_exec);
+        graph_exec = nullptr;
+      }
+      const uint32_t groups = (uint32_t)(lanes / kBlockThreads);
+      hipGraph_t g = nullptr;
+      FPT_HIP(hipStreamBeginCapture(graph_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t cap_err = hipSuccess;
+      for (int i = 0; i < group && cap_err == hipSuccess; ++i)
+        cap_err = launch_slice(fp64, model, R, multi, a, groups, graph_stream);
+      if (cap_err == hipSuccess)
+        cap_err = hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
+                                 graph_stream);
+      hipError_t end_err = hipStreamEndCapture(graph_stream, &g);
+      if (cap_err != hipSuccess || end_err != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(FPT_E_DEVICE, "graph capture failed: %s",
+                    hipGetErrorString(cap_err != hipSuccess ? cap_err : end_err));
+      }
+      hipError_t inst = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (inst != hipSuccess)
+        return fail(FPT_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(inst));
+      return FPT_OK;
+    };
+    FPT_TRY(capture());
     while (!finished) {
       FPT_HIP(hipEventRecord(events[0], graph_stream));
       FPT_HIP(hipGraphLaunch(graph_exec, graph_stream));
@@ -386,12 +448,18 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       if (!finished && (uint64_t)launches > bound)
         return fail(FPT_E_DEVICE, "run did not finish within %llu launches",
                     (unsigned long long)bound);
+      if (!finished) {
+        bool compacted = false;
+        FPT_TRY(maybe_compact(ws, a, buf, lanes, R, graph_stream, &compacted));
+        if (compacted) FPT_TRY(capture());
+      }
     }
     FPT_HIP(hipEventRecord(events[3], graph_stream));
     FPT_HIP(hipStreamWaitEvent(st, events[3], 0));
   } else {
     while (!finished) {
       FPT_TRY(ensure_host_resources(ev_used + 2 * group + 1));
+      const uint32_t groups = (uint32_t)(lanes / kBlockThreads);
       for (int i = 0; i < group; ++i) {
         hipEvent_t e0 = events[ev_used++], e1 = events[ev_used++];
         FPT_HIP(hipEventRecord(e0, st));
@@ -415,6 +483,10 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       if (!finished && (uint64_t)launches > bound)
         return fail(FPT_E_DEVICE, "run did not finish within %llu launches",
                     (unsigned long long)bound);
+      if (!finished) {
+        bool compacted = false;
+        FPT_TRY(maybe_compact(ws, a, buf, lanes, R, st, &compacted));
+      }
       group = std::min(group * 2, 8);
     }
   }

@@ -181,6 +181,37 @@ def test_results_independent_of_launch_shape(prec):
             assert r.moments[0][k] == base.moments[0][k], (t, k)
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_tail_compaction_keeps_results(prec):
+    # exponential escape times: once the queue is drained the active replicas
+    # thin out and move to a dense prefix of lanes, possibly several times
+    p = workloads.uneven_overdamped(n_replicas=20000, seed=12)
+    p["max_steps"] = 400_001
+    ref = api.simulate(p, prec, dict(replicas_per_lane=1, waves_per_simd=4, steps_per_launch=2048,
+                                     no_compaction=1))
+    assert ref.stats["n_compactions"] == 0
+    for t in (dict(replicas_per_lane=1, waves_per_simd=4, steps_per_launch=2048),
+              dict(replicas_per_lane=2, waves_per_simd=2, steps_per_launch=1024),
+              dict(replicas_per_lane=1, waves_per_simd=4, steps_per_launch=2048, use_graph=1)):
+        r = api.simulate(p, prec, t)
+        assert r.stats["n_compactions"] >= 1, t
+        assert r.stats["replica_steps"] / r.stats["lane_steps"] > \
+            ref.stats["replica_steps"] / ref.stats["lane_steps"]
+        assert np.array_equal(_steps(r), _steps(ref)), t
+        assert r.counts[0].tolist() == ref.counts[0].tolist()
+        for k in INT_MOMENTS:
+            assert r.moments[0][k] == ref.moments[0][k], (t, k)
+    # several sets in one plan
+    sets = workloads.batched_sets(n_sets=5, seed=6, log2_min=8, log2_max=11, ramp_scale=300.0)
+    b0 = api.simulate(sets, prec, dict(replicas_per_lane=1, waves_per_simd=2,
+                                       steps_per_launch=2048, no_compaction=1))
+    b1 = api.simulate(sets, prec, dict(replicas_per_lane=1, waves_per_simd=2,
+                                       steps_per_launch=2048))
+    for i in range(len(sets)):
+        assert np.array_equal(_steps(b0, i), _steps(b1, i)), i
+        assert b0.counts[i].tolist() == b1.counts[i].tolist()
+
+
 def test_uneven_overdamped_fp64_sample_matches_oracle():
     p = workloads.uneven_overdamped(n_replicas=2 ** 14, seed=3)
     gpu = _steps(api.simulate(p, "fp64", FIXED))
