@@ -256,7 +256,9 @@ def uneven_mode(args):
     steps = None
     for sched in ("refill", "one_per_lane"):
         tun = dict(schedule=0 if sched == "refill" else 1)
-        api.simulate(dict(p, n_replicas=min(p["n_replicas"], 2 ** 16), seed=77), "fp32c", tun,
+        # untimed: library load and the tuner's trials, on the same replicas
+        # (the tuner keys its cache by plan size), cut short by a step cap
+        api.simulate(dict(p, seed=77, max_steps=20_000, hist_k_max=20_000), "fp32c", tun,
                      record_steps=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -297,8 +299,9 @@ def batched_mode(args):
     res = {}
     for graph in (1, 0):
         tun = dict(use_graph=graph)
-        api.simulate(workloads.batched_sets(n_sets=256, seed=4, ramp_scale=1000.0), "fp32c",
-                     tun, record_steps=False)
+        api.simulate([dict(x, max_steps=min(x["max_steps"], 20_000),
+                           hist_k_max=min(x["hist_k_max"] or x["max_steps"], 20_000))
+                      for x in sets], "fp32c", tun, record_steps=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = api.simulate(sets, "fp32c", tun, record_steps=False)

@@ -171,8 +171,13 @@ fpt_status Plan::resolve_tuning(char* ws, hipStream_t st) {
   TuneEntry best;
   bool have_rate = false;
   if (need_r || need_w || need_s) {
-    const std::string key =
-        tune_key(arch, precision, model, t.schedule, multi) + (mt ? "/mt19937" : "");
+    // the size class matters: below the chip's lane capacity every wave
+    // count gives the same lane count, so a small plan's winner says nothing
+    // about a large one
+    int size_class = 0;
+    for (uint64_t n = total_flat; n > 1; n >>= 1) ++size_class;
+    const std::string key = tune_key(arch, precision, model, t.schedule, multi) + "/n" +
+                            std::to_string(size_class) + (mt ? "/mt19937" : "");
     TuneEntry cached;
     if (tune_lookup(key, &cached)) {
       if (need_r) t.replicas_per_lane = cached.replicas_per_lane;

@@ -317,6 +317,20 @@ uint64_t Plan::launch_bound(uint64_t n_slots, int blocks) const {
   return 2 * (spread + longest / (uint64_t)blocks + 1) + 16;
 }
 
+// Once no undrawn replica is left (and compaction is on), the run checks for
+// compaction after every launch and launches a quarter as many steps, so the
+// launch width can follow the decay of the active replicas.  Returns true
+// when it changes the launches.
+bool Plan::tail_launches(SliceArgs& a) {
+  if (!has_alt || tuning.no_compaction || !a.refill || h_ctr->cursor < total_flat)
+    return false;
+  const int32_t shorter = std::max<int32_t>(16, a.blocks / 4);
+  if (tail_mode || shorter == a.blocks) return false;
+  tail_mode = true;
+  a.blocks = shorter;
+  return true;
+}
+
 // Tail compaction between launches (the counters in h_ctr are current): when
 // no undrawn replica is left and the active ones fill at most half of the
 // slots, count them, and if the launch can narrow by a quarter or more, move
@@ -386,8 +400,11 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
 
   uint64_t lanes = n_lanes;  // narrows at each tail compaction
   int buf = 0;
+  tail_mode = false;
   const bool fp64 = precision == FPT_FP64;
-  const uint64_t bound = launch_bound(n_slots, blocks);
+  // the bound is on 4-step blocks issued, so shorter tail launches count less
+  const uint64_t bound_blocks = launch_bound(n_slots, blocks) * (uint64_t)blocks;
+  uint64_t blocks_issued = 0;
   stats = fpt_run_stats{};
   stats.tuning = tuning;
   int group = 1;
@@ -444,14 +461,17 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       FPT_HIP(hipEventElapsedTime(&ms, events[0], events[1]));
       kernel_ms += ms;
       launches += group;
+      blocks_issued += (uint64_t)group * (uint64_t)a.blocks;
       finished = h_ctr->done >= total_replicas;
-      if (!finished && (uint64_t)launches > bound)
-        return fail(FPT_E_DEVICE, "run did not finish within %llu launches",
-                    (unsigned long long)bound);
+      if (!finished && blocks_issued > bound_blocks)
+        return fail(FPT_E_DEVICE, "run did not finish within %llu steps per slot",
+                    (unsigned long long)(4 * bound_blocks));
       if (!finished) {
         bool compacted = false;
         FPT_TRY(maybe_compact(ws, a, buf, lanes, R, graph_stream, &compacted));
-        if (compacted) FPT_TRY(capture());
+        const bool shorter = tail_launches(a);
+        if (shorter) group = 1;
+        if (compacted || shorter) FPT_TRY(capture());
       }
     }
     FPT_HIP(hipEventRecord(events[3], graph_stream));
@@ -467,6 +487,7 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
         FPT_HIP(hipEventRecord(e1, st));
         marks.emplace_back(e0, e1);
         ++launches;
+        blocks_issued += (uint64_t)a.blocks;
       }
       FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
       hipEvent_t sync = events[ev_used++];
@@ -480,14 +501,15 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       marks.clear();
       ev_used = 0;
       finished = h_ctr->done >= total_replicas;
-      if (!finished && (uint64_t)launches > bound)
-        return fail(FPT_E_DEVICE, "run did not finish within %llu launches",
-                    (unsigned long long)bound);
+      if (!finished && blocks_issued > bound_blocks)
+        return fail(FPT_E_DEVICE, "run did not finish within %llu steps per slot",
+                    (unsigned long long)(4 * bound_blocks));
       if (!finished) {
         bool compacted = false;
         FPT_TRY(maybe_compact(ws, a, buf, lanes, R, st, &compacted));
       }
       group = std::min(group * 2, 8);
+      if (!finished && tail_launches(a)) group = 1;
     }
   }
   if (total_replicas == 0) FPT_TRY(ensure_host_resources(1));
