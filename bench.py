@@ -118,12 +118,14 @@ def parse():
     ap.add_argument("--serve-rho", type=float, default=0.7,
                     help="offered load of the rate-scaled trace, as a fraction of the "
                          "measured FP32C throughput")
-    ap.add_argument("--mode", choices=("switching", "uneven", "batched", "mt"),
+    ap.add_argument("--mode", choices=("switching", "uneven", "batched", "mt", "next"),
                     default="switching",
                     help="switching: the benchmark line (default); uneven: refill vs "
                          "one-replica-per-lane on the uneven overdamped workload; batched: "
                          "the 256-set workload in one graph-replayed persistent launch; mt: "
-                         "the switching workload with per-replica MT19937 against Philox")
+                         "the switching workload with per-replica MT19937 against Philox; "
+                         "next: rates of the semi-implicit scheme and of the Arrhenius and "
+                         "switching-distribution analyses")
     ap.add_argument("--ramp-scale", type=float, default=1.0,
                     help="batched mode: multiply every ramp (shorter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -378,6 +380,55 @@ def mt_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def next_mode(args):
+    """Rates of the extensions beyond the plain method: the semi-implicit
+    scheme on the benchmark workload (against the explicit one), an
+    Arrhenius sweep (one batched plan over temperatures) and a
+    switching-distribution run at the Li07 damping and temperature."""
+    import torch
+
+    from paper_1802_05065_amd import analysis, api, workloads
+
+    n = args.replicas if args.replicas != 2 ** 20 else 2 ** 18
+    out = {"replicas": n, "precision": "fp32c"}
+    for scheme in (0, 1):
+        api.simulate(workloads.switching_ramp(n_replicas=n, seed=99) | dict(
+            ramp=1e-3, max_steps=20_100, hist_k_max=20_000, scheme=scheme), "fp32c",
+            record_steps=False)
+        plan = api.Plan([workloads.switching_ramp(n_replicas=n, seed=2) | dict(scheme=scheme)],
+                        "fp32c", None, torch.device("cuda", 0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = plan.run(record_steps=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = r.stats
+        out["semi_implicit" if scheme else "explicit"] = {
+            "replica_steps_per_s": st["replica_steps"] / (t1 - t0),
+            "kernel_replica_steps_per_s": st["replica_steps"] / (st["kernel_ms"] * 1e-3),
+            "mean_switch_step": r.moments[0]["sum_k"] / max(r.moments[0]["n_escaped"], 1),
+            "tuning": st["tuning"]}
+    g = 0.5
+    du = float(analysis.barrier_height(g))
+    temps = [du / x for x in (4.0, 5.0, 6.0, 7.0)]
+    analysis.arrhenius_sweep(g, 0.5, temps, n_replicas=512, dt=0.02)  # tuning, untimed
+    t0 = time.perf_counter()
+    arr = analysis.arrhenius_sweep(g, 0.5, temps, n_replicas=4096, dt=0.02)
+    t1 = time.perf_counter()
+    out["arrhenius"] = {"wall_s": t1 - t0, "replica_steps": arr["stats"]["replica_steps"],
+                        "replica_steps_per_s": arr["stats"]["replica_steps"] / (t1 - t0),
+                        "delta_U": arr["delta_U"], "delta_U_fit": arr["delta_U_arrhenius"]}
+    for scheme in (1, 0):
+        t0 = time.perf_counter()
+        sw = analysis.switching_distribution(alpha=0.283, T=0.0673, ramp=1e-6, n_replicas=30000,
+                                             dt=0.02, scheme=scheme)
+        t1 = time.perf_counter()
+        out[f"switching_cdf_scheme{scheme}"] = {
+            "wall_s": t1 - t0, "replica_steps_per_s": sw["stats"]["replica_steps"] / (t1 - t0),
+            "max_abs_diff_fd": sw["max_abs_diff"], "mean_gamma_sw": sw["mean_gamma_sw"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -395,6 +446,9 @@ def main():
         return
     if args.mode == "mt":
         mt_mode(args)
+        return
+    if args.mode == "next":
+        next_mode(args)
         return
     import numpy as np
     import torch
