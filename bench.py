@@ -411,7 +411,8 @@ def next_mode(args):
     g = 0.5
     du = float(analysis.barrier_height(g))
     temps = [du / x for x in (4.0, 5.0, 6.0, 7.0)]
-    analysis.arrhenius_sweep(g, 0.5, temps, n_replicas=512, dt=0.02)  # tuning, untimed
+    analysis.arrhenius_sweep(g, 0.5, temps, n_replicas=4096, dt=0.02,
+                             max_steps=20_000)  # tuning on the same plan size, untimed
     t0 = time.perf_counter()
     arr = analysis.arrhenius_sweep(g, 0.5, temps, n_replicas=4096, dt=0.02)
     t1 = time.perf_counter()
