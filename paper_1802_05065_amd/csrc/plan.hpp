@@ -11,6 +11,9 @@
 
 namespace fpt {
 
+// Launches near the end of a refill run are this many times shorter.
+constexpr int32_t kTailLaunchDivisor = 8;
+
 struct Plan {
   std::vector<fpt_params> params;
   std::vector<SetDev> sets;     // derived constants, hist offsets
@@ -56,7 +59,7 @@ struct Plan {
   SliceArgs slice_args(char* ws, uint64_t* hist, uint64_t n_lanes, int buf = 0) const;
   fpt_status maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes, int R,
                            hipStream_t st, bool* compacted);
-  bool tail_launches(SliceArgs& a);
+  bool tail_launches(SliceArgs& a, uint64_t slots);
   bool tail_mode = false;
   uint64_t lanes_for(const fpt_tuning& t) const;
   int resident_waves(int R) const;

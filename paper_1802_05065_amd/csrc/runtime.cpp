@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -317,14 +318,15 @@ uint64_t Plan::launch_bound(uint64_t n_slots, int blocks) const {
   return 2 * (spread + longest / (uint64_t)blocks + 1) + 16;
 }
 
-// Once no undrawn replica is left (and compaction is on), the run checks for
-// compaction after every launch and launches a quarter as many steps, so the
-// launch width can follow the decay of the active replicas.  Returns true
-// when it changes the launches.
-bool Plan::tail_launches(SliceArgs& a) {
-  if (!has_alt || tuning.no_compaction || !a.refill || h_ctr->cursor < total_flat)
+// When fewer undrawn replicas are left than there are slots (and compaction
+// is on), the run checks for compaction after every launch and launches an
+// eighth as many steps, so the launch width can follow the decay of the
+// active replicas from the moment the queue drains.  Returns true when it
+// changes the launches.
+bool Plan::tail_launches(SliceArgs& a, uint64_t slots) {
+  if (!has_alt || tuning.no_compaction || !a.refill || h_ctr->cursor + slots < total_flat)
     return false;
-  const int32_t shorter = std::max<int32_t>(16, a.blocks / 4);
+  const int32_t shorter = std::max<int32_t>(16, a.blocks / kTailLaunchDivisor);
   if (tail_mode || shorter == a.blocks) return false;
   tail_mode = true;
   a.blocks = shorter;
@@ -332,9 +334,13 @@ bool Plan::tail_launches(SliceArgs& a) {
 }
 
 // Tail compaction between launches (the counters in h_ctr are current): when
-// no undrawn replica is left and the active ones fill at most half of the
-// slots, count them, and if the launch can narrow by a quarter or more, move
-// their state to a dense prefix of the other state buffer.
+// no undrawn replica is left and the active ones fill at most 80% of the
+// slots, count them, and if the launch can narrow by a tenth or more, move
+// their state to a dense prefix of the other state buffer.  (Thresholds
+// from a sweep on the uneven and batched workloads: 50%/25% left 8% of the
+// batched run's lane-steps idle, 80%/10% leaves 3%.)
+constexpr uint64_t kCompactTriggerPercent = 80;
+constexpr uint64_t kCompactNarrowPercent = 90;
 fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes, int R,
                                hipStream_t st, bool* compacted) {
   *compacted = false;
@@ -343,7 +349,7 @@ fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes
   const uint64_t slots = lanes * (uint64_t)R;
   const uint64_t done = (uint64_t)h_ctr->done;
   const uint64_t active_bound = total_flat - std::min<uint64_t>(done, total_flat);
-  if (active_bound * 2 > slots) return FPT_OK;
+  if (active_bound * 100 > slots * kCompactTriggerPercent) return FPT_OK;
   FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, st));
   FPT_HIP(launch_compact_count(a, slots, st));
   FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -351,7 +357,7 @@ fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes
   const uint64_t active = h_ctr->compact;
   const uint64_t new_lanes = std::max<uint64_t>(
       kBlockThreads, round_up((active + (uint64_t)R - 1) / (uint64_t)R, kBlockThreads));
-  if (new_lanes * 4 > lanes * 3) return FPT_OK;
+  if (new_lanes * 100 > lanes * kCompactNarrowPercent) return FPT_OK;
   SliceArgs dst = slice_args(ws, reinterpret_cast<uint64_t*>(a.hist), new_lanes, 1 - buf);
   dst.blocks = a.blocks;
   dst.refill = a.refill;
@@ -469,7 +475,7 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       if (!finished) {
         bool compacted = false;
         FPT_TRY(maybe_compact(ws, a, buf, lanes, R, graph_stream, &compacted));
-        const bool shorter = tail_launches(a);
+        const bool shorter = tail_launches(a, lanes * (uint64_t)R);
         if (shorter) group = 1;
         if (compacted || shorter) FPT_TRY(capture());
       }
@@ -509,7 +515,7 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
         FPT_TRY(maybe_compact(ws, a, buf, lanes, R, st, &compacted));
       }
       group = std::min(group * 2, 8);
-      if (!finished && tail_launches(a)) group = 1;
+      if (!finished && tail_launches(a, lanes * (uint64_t)R)) group = 1;
     }
   }
   if (total_replicas == 0) FPT_TRY(ensure_host_resources(1));
