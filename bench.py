@@ -271,7 +271,8 @@ def uneven_mode(args):
         util = st["replica_steps"] / st["lane_steps"] if st["lane_steps"] else None
         out[sched] = {"replica_steps_per_s": st["replica_steps"] / (t1 - t0),
                       "wall_s": t1 - t0, "lane_utilization": util,
-                      "launches": st["n_launches"], "tuning": st["tuning"]}
+                      "launches": st["n_launches"], "compactions": st["n_compactions"],
+                      "tuning": st["tuning"]}
         if steps is None:
             steps = r.steps[0].cpu().numpy()
         else:

@@ -59,8 +59,9 @@ struct Plan {
   SliceArgs slice_args(char* ws, uint64_t* hist, uint64_t n_lanes, int buf = 0) const;
   fpt_status maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes, int R,
                            hipStream_t st, bool* compacted);
-  bool tail_launches(SliceArgs& a, uint64_t slots);
+  bool tail_launches(SliceArgs& a, uint64_t slots, uint64_t draw_per_group);
   bool tail_mode = false;
+  uint64_t last_cursor = 0;     // cursor at the previous check
   uint64_t lanes_for(const fpt_tuning& t) const;
   int resident_waves(int R) const;
   uint64_t launch_bound(uint64_t n_slots, int blocks) const;

@@ -167,6 +167,12 @@ DeviceInfo device_info() {
 // ---------------------------------------------------------------------------
 // Plans
 
+// FPT_VERBOSE=1 prints run-time decisions (tail mode, compactions) to stderr.
+static bool verbose() {
+  const char* v = std::getenv("FPT_VERBOSE");
+  return v && v[0] == '1';
+}
+
 static uint64_t align256(uint64_t x) { return round_up(x, 256); }
 
 fpt_status Plan::layout() {
@@ -318,17 +324,23 @@ uint64_t Plan::launch_bound(uint64_t n_slots, int blocks) const {
   return 2 * (spread + longest / (uint64_t)blocks + 1) + 16;
 }
 
-// When fewer undrawn replicas are left than there are slots (and compaction
-// is on), the run checks for compaction after every launch and launches an
-// eighth as many steps, so the launch width can follow the decay of the
-// active replicas from the moment the queue drains.  Returns true when it
-// changes the launches.
-bool Plan::tail_launches(SliceArgs& a, uint64_t slots) {
-  if (!has_alt || tuning.no_compaction || !a.refill || h_ctr->cursor + slots < total_flat)
+// When fewer undrawn replicas are left than there are slots, or will be
+// after the next group of launches at the cursor's last rate of advance (and
+// compaction is on), the run checks for compaction after every launch and
+// launches an eighth as many steps, so the launch width can follow the decay
+// of the active replicas from the moment the queue drains.  Returns true
+// when it changes the launches.
+bool Plan::tail_launches(SliceArgs& a, uint64_t slots, uint64_t draw_per_group) {
+  if (!has_alt || tuning.no_compaction || !a.refill ||
+      h_ctr->cursor + slots + draw_per_group < total_flat)
     return false;
   const int32_t shorter = std::max<int32_t>(16, a.blocks / kTailLaunchDivisor);
   if (tail_mode || shorter == a.blocks) return false;
   tail_mode = true;
+  if (verbose())
+    std::fprintf(stderr, "[fpt] tail: %lld undrawn, %llu slots, launches %d -> %d blocks\n",
+                 (long long)total_flat - (long long)h_ctr->cursor, (unsigned long long)slots,
+                 a.blocks, shorter);
   a.blocks = shorter;
   return true;
 }
@@ -364,6 +376,10 @@ fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes
   dst.clamp = a.clamp;
   FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, st));
   FPT_HIP(launch_compact_move(a, dst, slots, new_lanes * (uint64_t)R, st));
+  if (verbose())
+    std::fprintf(stderr, "[fpt] compaction: %llu active slots, %llu -> %llu lanes\n",
+                 (unsigned long long)active, (unsigned long long)lanes,
+                 (unsigned long long)new_lanes);
   a = dst;
   buf = 1 - buf;
   lanes = new_lanes;
@@ -407,6 +423,7 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
   uint64_t lanes = n_lanes;  // narrows at each tail compaction
   int buf = 0;
   tail_mode = false;
+  last_cursor = std::min<uint64_t>(n_slots, total_flat);  // the cursor after reset_run
   const bool fp64 = precision == FPT_FP64;
   // the bound is on 4-step blocks issued, so shorter tail launches count less
   const uint64_t bound_blocks = launch_bound(n_slots, blocks) * (uint64_t)blocks;
@@ -472,10 +489,12 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       if (!finished && blocks_issued > bound_blocks)
         return fail(FPT_E_DEVICE, "run did not finish within %llu steps per slot",
                     (unsigned long long)(4 * bound_blocks));
+      const uint64_t advance = h_ctr->cursor - std::min<uint64_t>(h_ctr->cursor, last_cursor);
+      last_cursor = h_ctr->cursor;
       if (!finished) {
         bool compacted = false;
         FPT_TRY(maybe_compact(ws, a, buf, lanes, R, graph_stream, &compacted));
-        const bool shorter = tail_launches(a, lanes * (uint64_t)R);
+        const bool shorter = tail_launches(a, lanes * (uint64_t)R, advance);
         if (shorter) group = 1;
         if (compacted || shorter) FPT_TRY(capture());
       }
@@ -510,12 +529,17 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       if (!finished && blocks_issued > bound_blocks)
         return fail(FPT_E_DEVICE, "run did not finish within %llu steps per slot",
                     (unsigned long long)(4 * bound_blocks));
+      const uint64_t advance = h_ctr->cursor - std::min<uint64_t>(h_ctr->cursor, last_cursor);
+      const uint64_t per_launch = advance / (uint64_t)group;
+      last_cursor = h_ctr->cursor;
       if (!finished) {
         bool compacted = false;
         FPT_TRY(maybe_compact(ws, a, buf, lanes, R, st, &compacted));
       }
       group = std::min(group * 2, 8);
-      if (!finished && tail_launches(a, lanes * (uint64_t)R)) group = 1;
+      if (!finished &&
+          (tail_mode || tail_launches(a, lanes * (uint64_t)R, per_launch * (uint64_t)group)))
+        group = 1;
     }
   }
   if (total_replicas == 0) FPT_TRY(ensure_host_resources(1));
