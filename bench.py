@@ -78,10 +78,11 @@ def mix_attainable(mix=FP32C_BLOCK_MIX):
     return 4.0 / block_s
 
 
-def counter_traffic(slots: int):
-    """HBM bytes per launch of the FP32C slice kernel from the committed
-    FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel sources
-    (or the launch shape) differ from those the counters were taken on."""
+def counter_traffic():
+    """Mean HBM bytes per launch of the FP32C slice kernel over the timed run,
+    from the committed FETCH_SIZE / WRITE_SIZE counter runs of this command,
+    or None when the kernel sources differ from those the counters were
+    taken on."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "slice_kernel_traffic.json")
@@ -90,7 +91,7 @@ def counter_traffic(slots: int):
         h = hashlib.sha256()
         for src in rec["kernel_sources"]:
             h.update(open(os.path.join(ROOT, src), "rb").read())
-        if h.hexdigest() != rec["kernel_sources_sha256"] or int(rec["slots"]) != slots:
+        if h.hexdigest() != rec["kernel_sources_sha256"]:
             return None
         return float(rec["bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -523,9 +524,7 @@ def main():
     achieved = st["replica_steps"] * OPS_FP32C / kernel_s if kernel_s > 0 else 0.0
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
             "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS,
-            "traffic": counter_traffic(
-                torch.cuda.get_device_properties(0).multi_processor_count * 4 * 64
-                * st["tuning"]["waves_per_simd"] * st["tuning"]["replicas_per_lane"]),
+            "traffic": counter_traffic(),
             "kernel": "slice_kernel<fp32c, underdamped>",
             "ops_per_replica_step": OPS_FP32C,
             "mix_attainable_replica_steps_per_s": mix_attainable(),
