@@ -40,6 +40,12 @@ OPS_FP32C = (40 + 8 + 10 + 5 + 36 + 2) / 4.0
 # MI355X FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-operations/s
 # (256 CUs x 128 FP32 lanes per clock x 2.4 GHz)
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# FP64 flops per replica-step of the FP64 kernel as compiled (software sin,
+# log, sqrt, sin/cos at full accuracy): 51.0 adds + 24.1 multiplies + 37.7
+# FMAs (2 flops) per step from its SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 counters
+# (profiles/slice_kernel_fp64_switching_2p18.md); peak 78.6 TFLOP/s.
+FP64_FLOPS_PER_STEP = 51.0 + 24.1 + 2 * 37.7
+PEAK_FP64_FLOPS = 78.6e12
 
 
 # Instructions per 4-step block of one replica as the FP32C underdamped kernel
@@ -282,10 +288,17 @@ def uneven_mode(args):
     k = steps[steps > 0].astype(np.float64)
     rng = np.random.Generator(np.random.PCG64(0))
     emp = k.mean() / rng.choice(k, size=(20000, lanes)).max(axis=1).mean()
+    per_slot = p["n_replicas"] / (out["refill"]["tuning"]["waves_per_simd"] * 4 * 64 *
+                                  torch.cuda.get_device_properties(0).multi_processor_count *
+                                  out["refill"]["tuning"]["replicas_per_lane"])
     out["appendix_a"] = {
         "threads": lanes,
         "exponential_model_efficiency": appendix_a.efficiency(lanes, 1),
         "empirical_escape_law_efficiency": float(emp),
+        "static_partition_efficiency": appendix_a.efficiency(lanes, max(1, round(per_slot))),
+        "static_partition_note": "Appendix A's model with each of the 64 threads of a "
+                                 "wavefront given a fixed share of round(replicas per slot) "
+                                 "jobs; refill assigns them dynamically instead",
         "note": "one replica per lane: a wavefront's slots wait for its slowest replica; "
                 "Appendix A models escape times as unit exponentials (efficiency 1/H_N)"}
     out["identical_results_across_schedules"] = True
@@ -506,6 +519,22 @@ def main():
     f1 = time.perf_counter()
     value64 = r64.stats["replica_steps"] / (f1 - f0)
     steps64 = r64.steps[0].cpu().numpy()
+    f64_kernel = r64.stats["replica_steps"] / (r64.stats["kernel_ms"] * 1e-3)
+    roof64 = {"bound": "alu", "achieved": f64_kernel * FP64_FLOPS_PER_STEP / 1e12,
+              "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s",
+              "frac": f64_kernel * FP64_FLOPS_PER_STEP / PEAK_FP64_FLOPS,
+              "flops_per_replica_step": FP64_FLOPS_PER_STEP}
+    # same-seed paired error of FP32C against FP64 on the first 2^14 replicas
+    n_pair = min(2 ** 14, args.replicas)
+    pair64 = api.simulate(workloads.switching_ramp(n_replicas=n_pair, seed=2), "fp64")
+    k64 = pair64.steps[0].cpu().numpy()
+    k32 = steps32[:n_pair]
+    both = (k64 > 0) & (k32 > 0)
+    dk = np.abs(k32[both] - k64[both]).astype(np.float64)
+    paired = {"replicas": n_pair, "identical_fraction": float(np.mean(k32 == k64)),
+              "mean_abs_dk_steps": float(dk.mean()) if dk.size else None,
+              "max_abs_dk_steps": float(dk.max()) if dk.size else None,
+              "max_abs_dgamma_sw": float(dk.max() * p64["ramp"] * p64["dt"]) if dk.size else None}
     print(f"[bench] fp64 {args.fp64_replicas} replicas: {value64:.4e} replica-steps/s",
           file=sys.stderr, flush=True)
 
@@ -552,10 +581,13 @@ def main():
                                "gamma = 1e-6 t from 0, dt 0.05, threshold 2 pi, 256 bins",
                    "replicas": args.replicas, "precision": "fp32c",
                    "tuning": st["tuning"]},
+        "kernel_value": st["replica_steps"] / kernel_s if kernel_s > 0 else None,
         "fp64": {"value": value64, "replicas": args.fp64_replicas,
+                 "kernel_value": f64_kernel,
                  "speedup_fp32c_over_fp64": value / value64 if value64 > 0 else None,
-                 "tuning": r64.stats["tuning"]},
+                 "tuning": r64.stats["tuning"], "roofline": roof64},
         "ks": ks_info,
+        "paired_error_vs_fp64": paired,
         "latency": latency,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -347,3 +347,12 @@ def test_uneven_full_size_fp64_sampled():
     idx = np.linspace(0, p["n_replicas"] - 1, 64).astype(np.int64)
     ref = np.array([oracle.escape_steps(_op(p), int(i), 1)[0] for i in idx])
     assert np.mean(gpu[idx] == ref) >= 0.99
+
+
+def test_switching_fp64_subset_matches_oracle():
+    # the benchmark workload's first replicas in the literal FP64 path
+    p = workloads.switching_ramp(n_replicas=256, seed=2)
+    gpu = _steps(api.simulate(p, "fp64", None))
+    ref = oracle.escape_steps(_op(p), 0, 16)
+    assert np.mean(gpu[:16] == ref) >= 0.99
+    assert (gpu > 0).all()
