@@ -3,21 +3,27 @@ Josephson junction in a tilted washboard potential (arXiv:1802.05065).
 
 The compute path is the C ABI of ``include/fpt.h`` implemented in HIP
 (``csrc/``); this package holds its ctypes binding (``_lib``), PyTorch
-plumbing for device memory and streams (``api``), the seeded workloads
-(``workloads``) and the build script (``build``).
+plumbing for device memory and streams (``api``), the physics analyses built
+on it (``analysis``), the seeded workloads (``workloads``) and the build
+script (``build``).
 """
 
 from ._lib import (  # noqa: F401
     FPT_FP32C,
     FPT_FP64,
+    FPT_EXPLICIT,
     FPT_OVERDAMPED,
+    FPT_RNG_MT19937,
+    FPT_RNG_PHILOX,
     FPT_SCHED_ONE_PER_LANE,
     FPT_SCHED_REFILL,
+    FPT_SEMI_IMPLICIT,
     FPT_UNDERDAMPED,
     FptError,
     fpt_api_version,
     fpt_histogram,
     fpt_last_error,
+    fpt_mt_words,
     fpt_normals,
     fpt_plan,
     fpt_plan_destroy,
