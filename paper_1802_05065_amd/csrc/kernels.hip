@@ -421,7 +421,8 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
     const bool act = s[r].set != kInactive;
     if (MULTI && act) load_params(s[r], a.sets[s[r].set]);
     if constexpr (MT) {
-      mc[r] = MtCarry{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), 0u};
+      const uint4 z4 = make_uint4(0, 0, 0, 0);
+      mc[r] = MtCarry{z4, z4, z4, z4, 0u};
       if (act)
         mc[r] = mt_load(a.st_mt, n_slots, (uint64_t)r * a.n_lanes + lane_g,
                         (uint32_t)(s[r].j % kMtGroups));
@@ -557,7 +558,9 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
         const auto& p = MULTI ? s[r].p : uni.p;
         esc[r][0] = esc[r][1] = esc[r][2] = esc[r][3] = 0ull;
         const float top = fmaxf(fmaxf(ph_q[r][1], ph_q[r][2]), fmaxf(ph_q[r][3], ph_q[r][4]));
-        if (__ballot(top > p.th_near_rev)) {
+        // (active lanes only: a finished lane keeps its last phase until it
+        // takes a new replica)
+        if (__ballot(top > p.th_near_rev) & amask[r]) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const float ph = ph_q[r][q + 1];
@@ -784,7 +787,8 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
   Slot<FP64> s;
   start_replica(s, 0, replica, sd);
   load_params(s, sd);
-  MtCarry mc{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), 0u};
+  MtCarry mc{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0),
+             make_uint4(0, 0, 0, 0), 0u};
   if (mt) {
     mt_seed_slot(mt, 1, 0, mt_replica_seed(sd.seed, replica));
     mc = mt_load(mt, 1, 0, 0u);

@@ -8,7 +8,8 @@
 // they stand in memory at that moment, which is exactly what the in-place
 // bulk loop sees.  So the draws are identical to the reference generator, and
 // a 4-step block costs one 16-byte store and two 16-byte loads per lane
-// instead of a 2.5 KB sweep every 156 blocks.
+// instead of a 2.5 KB sweep every 156 blocks.  The loads run two blocks
+// ahead of their use, so that enough state is in flight to keep HBM busy.
 //
 // Layout (structure of arrays, coalesced over a wavefront): group g of the
 // state (words 4g .. 4g+3) of slot s is the uint4 at st[g * n_slots + s].
@@ -26,13 +27,18 @@ constexpr uint32_t kMtWords = 624;
 constexpr uint32_t kMtGroups = kMtWords / 4;  // 156
 constexpr uint32_t kMtFar = 99;               // word 397 = 4 * 99 + 1
 
-// Registers carried from block to block: the group being regenerated (as it
-// stands in memory) and the group holding words i+396 .. i+399.
+// Registers carried from block to block: the group being regenerated and
+// the next one (as they stand in memory), and the groups holding words
+// i+396 .. i+399 and i+400 .. i+403.
 struct MtCarry {
-  uint4 cur;
-  uint4 far;
+  uint4 cur, nxt;
+  uint4 far, far1;
   uint32_t g;  // group of the next block, j mod 156
 };
+
+__host__ __device__ __forceinline__ uint32_t mt_group(uint32_t g) {
+  return g < kMtGroups ? g : g - kMtGroups;
+}
 
 // Standard initialization: w0 = seed, w_i = 1812433253 (w_{i-1} ^ (w_{i-1} >> 30)) + i.
 __host__ __device__ inline void mt_seed_slot(uint4* st, uint64_t n_slots, uint64_t slot,
@@ -54,12 +60,13 @@ __host__ __device__ inline void mt_seed_slot(uint4* st, uint64_t n_slots, uint64
 
 // Carry registers for the block with group index g = j mod 156.
 __host__ __device__ __forceinline__ MtCarry mt_load(const uint4* st, uint64_t n_slots,
-                                           uint64_t slot, uint32_t g) {
+                                                   uint64_t slot, uint32_t g) {
   MtCarry c;
   c.g = g;
   c.cur = st[(uint64_t)g * n_slots + slot];
-  const uint32_t gf = g + kMtFar < kMtGroups ? g + kMtFar : g + kMtFar - kMtGroups;
-  c.far = st[(uint64_t)gf * n_slots + slot];
+  c.nxt = st[(uint64_t)mt_group(g + 1) * n_slots + slot];
+  c.far = st[(uint64_t)mt_group(g + kMtFar) * n_slots + slot];
+  c.far1 = st[(uint64_t)mt_group(g + kMtFar + 1) * n_slots + slot];
   return c;
 }
 
@@ -80,23 +87,23 @@ __host__ __device__ __forceinline__ uint32_t mt_temper(uint32_t y) {
 }
 
 // The 4 draws of one block: regenerate group c.g in memory and advance the
-// carry to the next group.
+// carry by one group.  The groups loaded here (g+2 and g+101) are used one
+// and two blocks later; neither is written in between (only g and g+1 are).
 __host__ __device__ __forceinline__ Words mt_block(uint4* st, uint64_t n_slots, uint64_t slot,
-                                          MtCarry& c) {
-  const uint32_t g1 = c.g + 1 < kMtGroups ? c.g + 1 : 0;
-  const uint32_t gf1 = c.g + kMtFar + 1 < kMtGroups ? c.g + kMtFar + 1
-                                                    : c.g + kMtFar + 1 - kMtGroups;
-  const uint4 nxt = st[(uint64_t)g1 * n_slots + slot];
-  const uint4 far1 = st[(uint64_t)gf1 * n_slots + slot];
+                                                  MtCarry& c) {
+  const uint4 nxt2 = st[(uint64_t)mt_group(c.g + 2) * n_slots + slot];
+  const uint4 far2 = st[(uint64_t)mt_group(c.g + kMtFar + 2) * n_slots + slot];
   uint4 n;
   n.x = mt_next_word(c.cur.x, c.cur.y, c.far.y);
   n.y = mt_next_word(c.cur.y, c.cur.z, c.far.z);
   n.z = mt_next_word(c.cur.z, c.cur.w, c.far.w);
-  n.w = mt_next_word(c.cur.w, nxt.x, far1.x);
+  n.w = mt_next_word(c.cur.w, c.nxt.x, c.far1.x);
   st[(uint64_t)c.g * n_slots + slot] = n;
-  c.cur = nxt;
-  c.far = far1;
-  c.g = g1;
+  c.cur = c.nxt;
+  c.nxt = nxt2;
+  c.far = c.far1;
+  c.far1 = far2;
+  c.g = mt_group(c.g + 1);
   Words w;
   w.w0 = mt_temper(n.x);
   w.w1 = mt_temper(n.y);
