@@ -203,7 +203,10 @@ void fpt_plan_destroy(fpt_plan_t plan);
  * device pool (`pool_bytes` at `device_pool`, which must stay allocated until
  * fpt_server_destroy).  Jobs are admitted as set slots and pool memory free
  * up; their replicas share the resident persistent lanes with the jobs
- * already running.  Errors: FPT_E_NOMEM if the pool cannot hold the fixed
+ * already running.  While every admitted replica has been drawn, the loop
+ * packs the running ones into fewer lanes as they finish (tail compaction),
+ * which speeds up each remaining replica; an admission restores the full
+ * width.  Errors: FPT_E_NOMEM if the pool cannot hold the fixed
  * lane state. */
 fpt_status fpt_server_create(void* device_pool, size_t pool_bytes,
                              int32_t precision, int32_t model,
@@ -228,6 +231,8 @@ typedef struct fpt_server_stats {
   uint64_t replica_steps;   /* of finished jobs */
   int64_t n_launches;
   double busy_s;            /* time with at least one job running */
+  int64_t n_compactions;    /* narrowings of the launch to the active slots
+                               while every admitted replica was drawn */
 } fpt_server_stats;
 
 fpt_status fpt_server_stats_get(fpt_server_t server, fpt_server_stats* out);

@@ -122,6 +122,7 @@ class FptServerStats(ctypes.Structure):
         ("replica_steps", ctypes.c_uint64),
         ("n_launches", ctypes.c_int64),
         ("busy_s", ctypes.c_double),
+        ("n_compactions", ctypes.c_int64),
     ]
 
 

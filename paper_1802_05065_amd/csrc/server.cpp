@@ -109,6 +109,13 @@ struct Server {
   uint64_t n_lanes = 0, n_slots = 0, ring = 0;
   uint64_t off_sets = 0, off_chunks = 0, off_ctr = 0, off_mom = 0;
   uint64_t off_st_phi = 0, off_st_v = 0, off_st_j = 0, off_st_idx = 0, off_st_set = 0;
+  // second lane-state buffer: when the ring is drained the active slots are
+  // compacted into a prefix of the other buffer and launches narrow to
+  // cur_lanes; appended work widens them again (the slots past the prefix
+  // are marked free in the whole buffer)
+  uint64_t off_alt[5] = {0, 0, 0, 0, 0};
+  int buf = 0;
+  uint64_t cur_lanes = 0;
   uint64_t off_hist = 0;
   RangeAlloc hist_alloc;
 
@@ -131,7 +138,9 @@ struct Server {
   bool busy = false;
   std::thread th;
 
-  SliceArgs args() const {
+  SliceArgs args() const { return args_for(buf, cur_lanes); }
+
+  SliceArgs args_for(int b, uint64_t lanes) const {
     SliceArgs a;
     std::memset(&a, 0, sizeof(a));
     a.sets = reinterpret_cast<const SetDev*>(pool + off_sets);
@@ -139,12 +148,15 @@ struct Server {
     a.chunk_mask = ring - 1;
     a.ctr = reinterpret_cast<Counters*>(pool + off_ctr);
     a.total = chunk_tail * kChunk;
-    a.st_phi = reinterpret_cast<unsigned long long*>(pool + off_st_phi);
-    a.st_v = reinterpret_cast<unsigned long long*>(pool + off_st_v);
-    a.st_j = reinterpret_cast<unsigned long long*>(pool + off_st_j);
-    a.st_idx = reinterpret_cast<unsigned long long*>(pool + off_st_idx);
-    a.st_set = reinterpret_cast<uint32_t*>(pool + off_st_set);
-    a.n_lanes = n_lanes;
+    const uint64_t o_phi = b ? off_alt[0] : off_st_phi, o_v = b ? off_alt[1] : off_st_v,
+                   o_j = b ? off_alt[2] : off_st_j, o_idx = b ? off_alt[3] : off_st_idx,
+                   o_set = b ? off_alt[4] : off_st_set;
+    a.st_phi = reinterpret_cast<unsigned long long*>(pool + o_phi);
+    a.st_v = reinterpret_cast<unsigned long long*>(pool + o_v);
+    a.st_j = reinterpret_cast<unsigned long long*>(pool + o_j);
+    a.st_idx = reinterpret_cast<unsigned long long*>(pool + o_idx);
+    a.st_set = reinterpret_cast<uint32_t*>(pool + o_set);
+    a.n_lanes = lanes;
     a.hist = reinterpret_cast<unsigned long long*>(pool + off_hist);
     a.mom = reinterpret_cast<MomDev*>(pool + off_mom);
     a.blocks = tuning.steps_per_launch / 4;
@@ -157,6 +169,7 @@ struct Server {
   void loop();
   fpt_status admit_locked(Job* j);
   fpt_status step();
+  fpt_status maybe_compact_locked();
   void finish_locked(Job* j, const MomDev& m);
 };
 
@@ -197,6 +210,12 @@ fpt_status Server::setup() {
   off_st_j = take(8 * n_slots);
   off_st_idx = take(8 * n_slots);
   off_st_set = take(4 * n_slots);
+  off_alt[0] = take(8 * n_slots);
+  off_alt[1] = take(8 * n_slots);
+  off_alt[2] = take(8 * n_slots);
+  off_alt[3] = take(8 * n_slots);
+  off_alt[4] = take(4 * n_slots);
+  cur_lanes = n_lanes;
   if (off + sizeof(Chunk) * kMinRingChunks + 8 * FPT_MAX_BINS > pool_bytes)
     return fail(FPT_E_NOMEM, "pool of %zu bytes cannot hold the lane state (%llu bytes) "
                 "plus a minimal work ring and one histogram", pool_bytes,
@@ -267,6 +286,7 @@ fpt_status Server::admit_locked(Job* j) {
   // pageable sources: make the copies complete before `ch` goes away
   FPT_HIP(hipStreamSynchronize(stream));
   chunk_tail += j->n_chunks;
+  cur_lanes = n_lanes;  // new work: full width again
   slot_job[(size_t)slot] = j;
   j->state = JobState::Running;
   ++stats.admitted;
@@ -305,7 +325,7 @@ fpt_status Server::step() {
     std::lock_guard<std::mutex> lk(mu);
     a = args();
   }
-  const uint32_t groups = (uint32_t)(n_lanes / kBlockThreads);
+  const uint32_t groups = (uint32_t)(a.n_lanes / kBlockThreads);
   FPT_HIP(hipEventRecord(ev0, stream));
   FPT_HIP(launch_slice(precision == FPT_FP64, model, tuning.replicas_per_lane, true, a, groups,
                        stream));
@@ -323,6 +343,37 @@ fpt_status Server::step() {
     const MomDev& m = h_mom[i];
     if (m.n_esc + m.n_cens >= (uint64_t)j->params.n_replicas) finish_locked(j, m);
   }
+  if (stats.running > 0) FPT_TRY(maybe_compact_locked());
+  return FPT_OK;
+}
+
+// With every appended replica drawn and the active ones filling at most 80%
+// of the current slots, move them to a dense prefix of the other lane-state
+// buffer (whose remaining slots, up to the full width, are marked free) and
+// narrow the launches; admit_locked widens them again.
+fpt_status Server::maybe_compact_locked() {
+  const uint64_t total = chunk_tail * kChunk;
+  if (h_ctr->cursor < total || cur_lanes <= (uint64_t)kBlockThreads) return FPT_OK;
+  const uint64_t R = (uint64_t)tuning.replicas_per_lane;
+  const uint64_t slots = cur_lanes * R;
+  const uint64_t active_bound = h_ctr->cursor - std::min<uint64_t>(h_ctr->cursor, h_ctr->done);
+  if (active_bound * 10 > slots * 8) return FPT_OK;
+  const SliceArgs a = args();
+  FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, stream));
+  FPT_HIP(launch_compact_count(a, slots, stream));
+  FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+  FPT_HIP(hipStreamSynchronize(stream));
+  const uint64_t active = h_ctr->compact;
+  const uint64_t lanes = std::max<uint64_t>(kBlockThreads,
+                                            round_up((active + R - 1) / R, kBlockThreads));
+  if (lanes * 10 > cur_lanes * 9) return FPT_OK;
+  SliceArgs dst = args_for(1 - buf, lanes);
+  FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, stream));
+  FPT_HIP(launch_compact_move(a, dst, slots, n_slots, stream));
+  FPT_HIP(hipStreamSynchronize(stream));
+  buf = 1 - buf;
+  cur_lanes = lanes;
+  ++stats.n_compactions;
   return FPT_OK;
 }
 

@@ -289,19 +289,30 @@ def test_serving_alone_equals_mix():
                                  dict(waves_per_simd=2, steps_per_launch=1024),
                                  stream.cuda_stream)
     try:
-        ids = [_lib.fpt_submit(srv, j) for j in jobs]
+        # three jobs, then (after the loop has drained its queue and packed
+        # the running replicas into fewer lanes) two more that widen it again
+        ids = {}
         results = {}
         t0 = time.time()
-        while len(results) < len(ids) and time.time() - t0 < 90:
-            for i, jid in enumerate(ids):
-                if i not in results:
-                    r = _lib.fpt_poll(srv, jid, jobs[i]["n_bins"])
-                    if r is not None:
-                        results[i] = r
-            time.sleep(0.01)
-        assert len(results) == len(ids)
+        for batch in ((0, 1, 2), (3, 4)):
+            for i in batch:
+                ids[i] = _lib.fpt_submit(srv, jobs[i])
+            if batch[0] == 0:
+                while _lib.fpt_server_stats_get(srv)["n_compactions"] == 0 and \
+                        time.time() - t0 < 60:
+                    time.sleep(0.005)
+            while len(results) < len(ids) and time.time() - t0 < 90:
+                for i, jid in ids.items():
+                    if i not in results:
+                        r = _lib.fpt_poll(srv, jid, jobs[i]["n_bins"])
+                        if r is not None:
+                            results[i] = r
+                time.sleep(0.01)
+        assert len(results) == len(jobs)
         st = _lib.fpt_server_stats_get(srv)
-        assert st["finished"] == len(ids)
+        print(f"server: {st['n_launches']} launches, {st['n_compactions']} compactions")
+        assert st["finished"] == len(jobs)
+        assert st["n_compactions"] >= 1
     finally:
         _lib.fpt_server_destroy(srv)
     for i, j in enumerate(jobs):
