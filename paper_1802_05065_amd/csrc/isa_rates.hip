@@ -60,7 +60,15 @@ constexpr int kThreads = 256;
   X(fmamk_f32, "v_fmamk_f32 %[x], %[x], 0x3f7fbe77, %[q]", 1)                         \
   X(mad_u64_u32_s0, "v_mad_u64_u32 %[d], vcc, %[x], %[ps], 0", 1)                     \
   X(bitop3_b32_s, "v_bitop3_b32 %[x], %[x], %[y], %[ps] bitop3:0x96", 1)               \
-  X(sub_f32, "v_sub_f32 %[x], %[x], %[y]", 1)
+  X(sub_f32, "v_sub_f32 %[x], %[x], %[y]", 1)                                         \
+  X(sqrt_f32_neg, "v_sqrt_f32_e64 %[x], -%[x]", 1)                                     \
+  X(log_f32_e64, "v_log_f32_e64 %[x], |%[x]|", 1)                                      \
+  X(alignbit_b32, "v_alignbit_b32 %[x], %[ps], %[x], 9", 1)                            \
+  X(max3_f32, "v_max3_f32 %[x], %[x], %[y], %[p]", 1)                                  \
+  X(max_f32, "v_max_f32 %[x], %[x], %[y]", 1)                                         \
+  X(cvt_f32_f64, "v_cvt_f32_f64 %[x], %[d]", 1)                                       \
+  X(sin_fmac_pair, "v_sin_f32 %[x], %[x]\n v_fmac_f32 %[y], %[ps], %[y]", 2)            \
+  X(sin_add_pair, "v_sin_f32 %[x], %[x]\n v_add_f32 %[y], %[y], %[p]", 2)
 
 #define DECL(name, text, n)                                                           \
   __global__ __launch_bounds__(kThreads) void k_##name(float* out, float seed) {     \
