@@ -54,14 +54,17 @@ PEAK_FP64_FLOPS = 78.6e12
 FP32C_BLOCK_MIX = {
     "mad_u64_u32_s0": 20,  # Philox products
     "bitop3_b32_s": 20,    # Philox three-input XORs
-    "sin_f32": 6, "cos_f32": 2, "log_f32": 2, "sqrt_f32": 2,
+    "sin_f32": 6, "cos_f32": 2, "log_f32": 2,
+    "sqrt_f32_neg": 2,     # Box-Muller radius, negated operand (VOP3 form)
     "fmac_f32_s": 13,      # Kahan increment, noise, force, damping
-    "add_f32": 9,          # Kahan sums, bias offsets, near-threshold max and compare
+    "add_f32": 8,          # Kahan sums, bias offsets, near-threshold compare
     "sub_f32": 7,          # Kahan error terms
     "mul_f32": 2, "fmamk_f32": 2,
-    "cvt_f32_u32": 3,      # uniforms, bias to FP32
-    "fma_f32_s": 3,        # other VOP3: angle bit-alignment, max3
-    "fma_f64": 1, "add_f64": 1,  # bias G_k and step count in FP64
+    "cvt_f32_u32": 2,      # uniforms of the radii
+    "cvt_f32_f64": 1,      # the block's bias G_k to FP32
+    "alignbit_b32": 2,     # uniforms of the angles
+    "max_f32": 1, "max3_f32": 1,  # largest phase of the block
+    "fma_f64": 1, "add_f64": 1,   # bias G_k and step count in FP64
     "add_u32": 2,          # block index
 }
 
