@@ -138,6 +138,8 @@ def parse():
                          "switching-distribution analyses")
     ap.add_argument("--ramp-scale", type=float, default=1.0,
                     help="batched mode: multiply every ramp (shorter runs)")
+    ap.add_argument("--no-regroup", action="store_true",
+                    help="batched mode: never move the active replicas into set order")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scale for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -318,7 +320,7 @@ def batched_mode(args):
     sets = workloads.batched_sets(n_sets=256, seed=4, ramp_scale=args.ramp_scale)
     res = {}
     for graph in (1, 0):
-        tun = dict(use_graph=graph)
+        tun = dict(use_graph=graph, no_regroup=int(args.no_regroup))
         api.simulate([dict(x, max_steps=min(x["max_steps"], 20_000),
                            hist_k_max=min(x["hist_k_max"] or x["max_steps"], 20_000))
                       for x in sets], "fp32c", tun, record_steps=False)
@@ -331,7 +333,11 @@ def batched_mode(args):
         res["graph" if graph else "stream"] = {
             "replica_steps_per_s": st["replica_steps"] / (t1 - t0), "wall_s": t1 - t0,
             "replica_steps": st["replica_steps"], "launches": st["n_launches"],
+            "kernel_s": st["kernel_ms"] / 1e3,
             "lane_utilization": st["replica_steps"] / max(st["lane_steps"], 1),
+            "regroups": st["n_regroups"], "compactions": st["n_compactions"],
+            # passes beyond one per wavefront block for lanes of other sets
+            "extra_pass_fraction": st["extra_passes"] / max(st["lane_steps"] / 256, 1),
             "tuning": st["tuning"],
             "censored": int(sum(m["n_censored"] for m in r.moments))}
         if graph:

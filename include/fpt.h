@@ -133,10 +133,16 @@ typedef struct fpt_tuning {
   int32_t use_graph;         /* 1: replay launches through a captured hipGraph */
   int32_t no_compaction;     /* 1: keep the launch width to the end.  Otherwise a
                                 refill plan (Philox) whose queue is drained and
-                                whose active replicas fill at most half the slots
-                                moves them to a dense prefix and narrows later
-                                launches; results do not change */
-  int32_t reserved[2];
+                                whose active replicas fill at most 80% of the
+                                slots moves them to a dense prefix and narrows
+                                later launches; results do not change */
+  int32_t no_regroup;        /* 1: never regroup.  Otherwise, when the lanes of a
+                                multi-set refill plan's wavefronts have come to
+                                hold replicas of several sets (a block then takes
+                                one pass per set), the active replicas' state is
+                                moved into set order between launches; results
+                                do not change */
+  int32_t reserved;
 } fpt_tuning;
 
 /* Per-set results.  Moments are over escaped replicas; times in units of t. */
@@ -155,6 +161,10 @@ typedef struct fpt_run_stats {
   double wall_ms;             /* fpt_simulate entry to last launch done */
   fpt_tuning tuning;          /* tuning actually used */
   int64_t n_compactions;      /* tail compactions of the last simulate */
+  int64_t n_regroups;         /* moves of the active state into set order */
+  uint64_t extra_passes;      /* multi-set blocks: passes beyond one per
+                                 wavefront and slot (lane_steps / 256 is the
+                                 number of wavefront-slot blocks) */
 } fpt_run_stats;
 
 typedef struct fpt_plan_s* fpt_plan_t;
@@ -233,6 +243,7 @@ typedef struct fpt_server_stats {
   double busy_s;            /* time with at least one job running */
   int64_t n_compactions;    /* narrowings of the launch to the active slots
                                while every admitted replica was drawn */
+  int64_t n_regroups;       /* moves of the active state into set order */
 } fpt_server_stats;
 
 fpt_status fpt_server_stats_get(fpt_server_t server, fpt_server_stats* out);

@@ -83,7 +83,8 @@ class FptTuning(ctypes.Structure):
         ("steps_per_launch", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("no_compaction", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("no_regroup", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -109,6 +110,8 @@ class FptRunStats(ctypes.Structure):
         ("wall_ms", ctypes.c_double),
         ("tuning", FptTuning),
         ("n_compactions", ctypes.c_int64),
+        ("n_regroups", ctypes.c_int64),
+        ("extra_passes", ctypes.c_uint64),
     ]
 
 
@@ -123,6 +126,7 @@ class FptServerStats(ctypes.Structure):
         ("n_launches", ctypes.c_int64),
         ("busy_s", ctypes.c_double),
         ("n_compactions", ctypes.c_int64),
+        ("n_regroups", ctypes.c_int64),
     ]
 
 
@@ -204,7 +208,8 @@ def make_tuning(t: Optional[Dict]) -> Optional[FptTuning]:
         return None
     return FptTuning(int(t.get("schedule", 0)), int(t.get("replicas_per_lane", 0)),
                      int(t.get("waves_per_simd", 0)), int(t.get("steps_per_launch", 0)),
-                     int(t.get("use_graph", 0)), int(t.get("no_compaction", 0)))
+                     int(t.get("use_graph", 0)), int(t.get("no_compaction", 0)),
+                     int(t.get("no_regroup", 0)))
 
 
 def moments_dict(m: FptMoments) -> Dict:
@@ -253,11 +258,12 @@ def fpt_plan_stats(plan: int) -> Dict:
     t = s.tuning
     return dict(replica_steps=s.replica_steps, lane_steps=s.lane_steps,
                 n_launches=s.n_launches, kernel_ms=s.kernel_ms, wall_ms=s.wall_ms,
-                n_compactions=s.n_compactions,
+                n_compactions=s.n_compactions, n_regroups=s.n_regroups,
+                extra_passes=s.extra_passes,
                 tuning=dict(schedule=t.schedule, replicas_per_lane=t.replicas_per_lane,
                             waves_per_simd=t.waves_per_simd,
                             steps_per_launch=t.steps_per_launch, use_graph=t.use_graph,
-                            no_compaction=t.no_compaction))
+                            no_compaction=t.no_compaction, no_regroup=t.no_regroup))
 
 
 def fpt_plan_destroy(plan: int) -> None:

@@ -127,6 +127,7 @@ static fpt_status trial(Plan& p, char* ws, hipStream_t st, const fpt_tuning& t,
   SliceArgs a = p.slice_args(ws, hist, lanes);
   a.blocks = 256;
   a.refill = refill ? 1 : 0;
+  a.whole_waves = p.regroups(t) ? 1 : 0;
   FPT_TRY(p.reset_run(a, lanes, R, refill, st));
   FPT_TRY(p.ensure_host_resources(3));
   const uint32_t groups = (uint32_t)(lanes / kBlockThreads);

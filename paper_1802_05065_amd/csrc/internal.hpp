@@ -71,7 +71,8 @@ struct alignas(16) Counters {
   unsigned long long done;        // replicas finished (escaped or censored)
   unsigned long long lane_steps;  // lane-steps issued, idle lanes included
   unsigned long long compact;     // active slots found by a compaction pass
-  unsigned long long pad[4];
+  unsigned long long extra_passes;  // multi-set blocks: passes beyond one per slot
+  unsigned long long pad[3];
 };
 
 // Arguments of one integrator launch.
@@ -93,7 +94,9 @@ struct SliceArgs {
   int32_t blocks;                 // 4-step blocks in this launch
   int32_t refill;                 // 1: take new replicas as slots free up
   int32_t clamp;                  // 1: cursor may not pass `total` (server)
-  int32_t pad;
+  int32_t whole_waves;            // 1: refill only wavefronts whose slot is free
+                                  // in every lane (multi-set runs that sort by set
+                                  // and refill between launches)
 };
 
 }  // namespace fpt

@@ -48,9 +48,6 @@ struct Slot<true> {
   double kd;  // 4 j + 1, the step number of the block's first step (exact)
   double phi, v;
   float e;    // unused in FP64
-  ParF64 p;
-  uint32_t k0, k1;
-  uint64_t jmax;
 };
 
 template <>
@@ -60,21 +57,43 @@ struct Slot<false> {
   double kd;
   float phi, v;  // phi: phase in revolutions
   float e;       // its Kahan error term: true phase = phi + e
-  ParF32 p;
-  uint32_t k0, k1;
-  uint64_t jmax;
 };
 
+// Constants of one set that the block loop reads, held in scalar registers:
+// a wavefront integrates a block for lanes of one set at a time.
 template <bool FP64>
-__device__ __forceinline__ void load_params(Slot<FP64>& s, const SetDev& sd) {
+struct SetPar;
+
+template <>
+struct SetPar<true> {
+  ParF64 p;
+  uint32_t k0, k1;  // Philox key: the set's seed
+};
+
+template <>
+struct SetPar<false> {
+  ParF32 p;
+  uint32_t k0, k1;
+};
+
+// The set table does not change while a launch runs; read through the
+// constant address space, a wavefront-uniform set index gives scalar loads.
+using ConstSetDev = const __attribute__((address_space(4))) SetDev;
+
+template <bool FP64>
+__device__ __forceinline__ SetPar<FP64> load_setpar(const SetDev* sets, uint32_t set) {
+  const ConstSetDev& d = ((ConstSetDev*)sets)[set];
+  SetPar<FP64> P;
   if constexpr (FP64) {
-    s.p = load_par_f64(sd);
+    P.p = ParF64{d.gamma0, d.dgamma, d.dt, d.alpha, d.V0, d.sigma, d.th};
   } else {
-    s.p = load_par_f32(sd);
+    P.p = ParF32{d.gA, d.gB, d.th_rev, d.h_rev_f, d.damp_f, d.nkS_f, d.sig_f, d.dG_f,
+                 d.dG2_f, d.dG3_f, d.th_near_rev_f};
   }
-  s.k0 = (uint32_t)sd.seed;
-  s.k1 = (uint32_t)(sd.seed >> 32);
-  s.jmax = sd.jmax;
+  const uint64_t seed = d.seed;
+  P.k0 = (uint32_t)seed;
+  P.k1 = (uint32_t)(seed >> 32);
+  return P;
 }
 
 template <bool FP64>
@@ -358,10 +377,11 @@ __device__ __forceinline__ uint32_t blocks_to_cap(const Slot<FP64>& sl, uint64_t
   return wave_min_u32(left);
 }
 
-// The 4 words of a slot's next block: Philox keyed by (block, replica), or
-// the next 4 outputs of the replica's MT19937 (active lanes only: a free
-// slot's state is re-seeded when it takes a replica).
-template <bool MT, bool UNIFORM_KEY, bool FP64>
+// The 4 words of a slot's next block: Philox keyed by (block, replica) with
+// the set's seed in scalar registers, or the next 4 outputs of the replica's
+// MT19937 (active lanes only: a free slot's state is re-seeded when it takes
+// a replica).
+template <bool MT, bool FP64>
 __device__ __forceinline__ Words block_words(const SliceArgs& a, uint64_t n_slots,
                                              uint64_t slot, bool active, MtCarry& mc,
                                              const Slot<FP64>& sl, uint32_t k0,
@@ -370,17 +390,216 @@ __device__ __forceinline__ Words block_words(const SliceArgs& a, uint64_t n_slot
     Words w{0u, 0u, 0u, 0u};
     if (active) w = mt_block(a.st_mt, n_slots, slot, mc);
     return w;
-  } else if constexpr (UNIFORM_KEY) {
+  } else {
     return philox4x32_10_uniform_key((uint32_t)sl.j, (uint32_t)(sl.j >> 32),
                                      (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32), k0, k1);
-  } else {
-    return philox4x32_10((uint32_t)sl.j, (uint32_t)(sl.j >> 32), (uint32_t)sl.idx,
-                         (uint32_t)(sl.idx >> 32), k0, k1);
   }
 }
 
+// Block index of the last allowed step of the slot's replica.
+template <bool MULTI, bool FP64>
+__device__ __forceinline__ uint64_t slot_jmax(const SliceArgs& a, const Slot<FP64>& sl,
+                                              bool active, uint64_t jmax_one) {
+  if constexpr (MULTI) {
+    return active ? a.sets[sl.set].jmax : 0ull;
+  } else {
+    return jmax_one;
+  }
+}
+
+// FP64: the 4 steps of a block for NR slots (r0 ... r0 + NR - 1) that share
+// the constants P.  Where step q ends above the threshold, bit q of
+// esc_bits[r] is set (PASS: the lanes of one pass of a multi-set block), or
+// the wavefront masks esc[r][q] are formed directly.
+template <int MODEL, int NR, bool MT, bool PASS>
+__device__ __forceinline__ void block_f64(const SliceArgs& a, uint64_t n_slots,
+                                          uint64_t lane_g, uint64_t lane_bit, int r0,
+                                          const uint64_t* amask, MtCarry* mc,
+                                          Slot<true>* s, const SetPar<true>& P,
+                                          uint32_t* esc_bits, uint64_t (*esc)[4]) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    Slot<true>& sl = s[r];
+    const Words w = block_words<MT>(a, n_slots, (uint64_t)(r0 + r) * a.n_lanes + lane_g,
+                                    (amask[r] & lane_bit) != 0, mc[r], sl, P.k0, P.k1);
+    double z[4];
+    normals_f64(w, z);
+    uint32_t bits = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double kd = sl.kd + (double)q;
+      if constexpr (MODEL == kUnderExplicit) {
+        step_f64_under(P.p, kd, z[q], sl.phi, sl.v);
+      } else if constexpr (MODEL == kUnderSemiImplicit) {
+        step_f64_under_si(P.p, kd, z[q], sl.phi, sl.v);
+      } else {
+        step_f64_over(P.p, kd, z[q], sl.phi);
+      }
+      if constexpr (PASS) {
+        bits |= (sl.phi > P.p.th) ? (1u << q) : 0u;
+      } else {
+        esc[r][q] = __ballot(sl.phi > P.p.th);
+      }
+    }
+    if constexpr (PASS) esc_bits[r] = bits;
+  }
+}
+
+// FP32C: the 4 steps of a block for NR slots sharing the constants P (gA:
+// P.p.gA in a vector register).  Records the phase after each step and the
+// compensated increments, from which the threshold test runs afterwards.
+template <int MODEL, int NR, bool MT>
+__device__ __forceinline__ void block_f32(const SliceArgs& a, uint64_t n_slots,
+                                          uint64_t lane_g, uint64_t lane_bit, int r0,
+                                          const uint64_t* amask, MtCarry* mc,
+                                          Slot<false>* s, const SetPar<false>& P, double gA,
+                                          float (*ph_q)[5], float (*y_q)[4]) {
+  const ParF32& p = P.p;
+  // generator and normals of every slot first, then the 4 steps with the
+  // slots interleaved (independent chains for the scheduler)
+  BoxMullerF32 bm[NR];
+  BlockG gk[NR];
+  float zs[NR][2];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    Slot<false>& sl = s[r];
+    const Words w = block_words<MT>(a, n_slots, (uint64_t)(r0 + r) * a.n_lanes + lane_g,
+                                    (amask[r] & lane_bit) != 0, mc[r], sl, P.k0, P.k1);
+    bm[r] = box_muller_f32(w);
+    gk[r] = block_g4(p, sl.kd, gA);
+    // all four bias terms exist before the first step, so every step can
+    // accumulate into its own (the first otherwise still feeds the rest)
+    asm volatile("" : "+v"(gk[r].g[0]), "+v"(gk[r].g[1]), "+v"(gk[r].g[2]),
+                 "+v"(gk[r].g[3]));
+    zs[r][0] = p.sig * bm[r].radius[0];
+    zs[r][1] = p.sig * bm[r].radius[1];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) ph_q[r][0] = s[r].phi;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      Slot<false>& sl = s[r];
+      const float trig = (q & 1) ? bm[r].s[q >> 1] : bm[r].c[q >> 1];
+      if constexpr (MODEL == kUnderExplicit) {
+        y_q[r][q] = step_f32_under(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e, sl.v);
+      } else if constexpr (MODEL == kUnderSemiImplicit) {
+        y_q[r][q] = step_f32_under_si(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e, sl.v);
+      } else {
+        y_q[r][q] = step_f32_over(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e);
+      }
+      ph_q[r][q + 1] = sl.phi;
+    }
+  }
+}
+
+// FP32C threshold test of one slot's block: one compare on the largest phase,
+// and the exact FP64 test of each step only where an active lane came near
+// the threshold (a finished lane keeps its last phase until it takes a new
+// replica).
+__device__ __forceinline__ void threshold_f32(const float (&ph_q)[5], const float (&y_q)[4],
+                                              float th_near_rev, double th_rev,
+                                              uint64_t amask, uint64_t (&esc)[4]) {
+  esc[0] = esc[1] = esc[2] = esc[3] = 0ull;
+  const float top = fmaxf(fmaxf(ph_q[1], ph_q[2]), fmaxf(ph_q[3], ph_q[4]));
+  if (__ballot(top > th_near_rev) & amask) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float ph = ph_q[q + 1];
+      // opaque copy: the error term is recomputed here, not kept live from
+      // the step (which would block the accumulate form there)
+      float y = y_q[q];
+      asm volatile("" : "+v"(y));
+      esc[q] = __ballot(ph > th_near_rev && above_f64(ph, kahan_error(y, ph, ph_q[q]), th_rev));
+    }
+  }
+}
+
+// The same test for the lanes of one pass of a multi-set block: bit q of the
+// result is set where step q ends above the threshold.
+__device__ __forceinline__ uint32_t threshold_bits_f32(const float (&ph_q)[5],
+                                                       const float (&y_q)[4],
+                                                       float th_near_rev, double th_rev) {
+  uint32_t bits = 0;
+  const float top = fmaxf(fmaxf(ph_q[1], ph_q[2]), fmaxf(ph_q[3], ph_q[4]));
+  if (__ballot(top > th_near_rev)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float ph = ph_q[q + 1];
+      float y = y_q[q];
+      asm volatile("" : "+v"(y));
+      if (ph > th_near_rev && above_f64(ph, kahan_error(y, ph, ph_q[q]), th_rev))
+        bits |= 1u << q;
+    }
+  }
+  return bits;
+}
+
+// End of a block for one slot: record the lanes whose replica crossed the
+// threshold in one of the 4 steps (esc) or reached its step cap, free their
+// slots, advance the block.  LANE_SET: the cap and step limit come from each
+// lane's set; otherwise from set set_u, shared by all lanes (read from the
+// table when needed, so they hold no registers through the block loop).
+template <bool LANE_SET, bool FP64>
+__device__ __forceinline__ void finish_slot(LdsTables& tab, const SliceArgs& a,
+                                            Slot<FP64>& sl, uint64_t& amask, uint32_t& safe,
+                                            const uint64_t (&esc)[4], uint64_t lane_bit,
+                                            uint32_t set_u) {
+  // set_u == kInactive: the set of the first active lane (all active lanes
+  // share it), found only where it is needed
+  if (!LANE_SET && set_u == kInactive)
+    set_u = amask ? (uint32_t)__builtin_amdgcn_readlane(
+                        (int)sl.set, __ffsll((unsigned long long)amask) - 1)
+                  : 0u;
+  const ConstSetDev& su = ((ConstSetDev*)a.sets)[set_u];
+  const uint64_t crossed = (esc[0] | esc[1] | esc[2] | esc[3]) & amask;
+  const bool check_cap = safe == 0;
+  uint64_t last = 0ull;
+  if (check_cap) {
+    const uint64_t jm = LANE_SET ? slot_jmax<true>(a, sl, (amask & lane_bit) != 0, 0ull) : su.jmax;
+    last = __ballot(sl.j >= jm) & amask;
+  }
+  if (crossed | last) {
+    bool fin = false;
+    int64_t k = -1;
+    if ((crossed | last) & lane_bit) {
+      int q1 = 0;
+      if (esc[0] & lane_bit) q1 = 1;
+      else if (esc[1] & lane_bit) q1 = 2;
+      else if (esc[2] & lane_bit) q1 = 3;
+      else if (esc[3] & lane_bit) q1 = 4;
+      const int64_t kesc = q1 ? (int64_t)(4 * sl.j) + q1 : 0;
+      const int64_t max_steps = LANE_SET ? a.sets[sl.set].max_steps : su.max_steps;
+      if (q1 && kesc <= max_steps) {
+        fin = true;
+        k = kesc;
+      } else if (sl.j >= (LANE_SET ? slot_jmax<true>(a, sl, true, 0ull) : su.jmax)) {
+        fin = true;
+        k = -1;
+      }
+    }
+    record_finished(tab, a, fin, sl.set, sl.idx, k);
+    if (fin) sl.set = kInactive;
+    amask &= ~__ballot(fin);
+  }
+  sl.j += 1;
+  sl.kd += 4.0;
+  if (check_cap) {
+    const bool act = (amask & lane_bit) != 0;
+    safe = blocks_to_cap(sl, LANE_SET ? slot_jmax<true>(a, sl, act, 0ull) : su.jmax, act);
+  } else {
+    --safe;
+  }
+}
+
+// A multi-set wavefront integrates a block in passes, one per distinct set
+// among the active lanes of a slot, each with that set's constants in scalar
+// registers (the Philox key among them).  Lanes are grouped by set between
+// launches, so nearly every block takes one pass; the passes beyond the first
+// are counted for the host.
 template <bool FP64, int MODEL, int R, bool MULTI, bool MT>
-__global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
+__device__ __forceinline__ void slice_body(const SliceArgs& a) {
   static_assert(!MT || (R == 1 && !MULTI), "MT19937 mode: one set, one slot per lane");
   __shared__ LdsTables tab;
   for (int i = threadIdx.x; i < kHistSlots; i += kBlockThreads) {
@@ -398,15 +617,19 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
   const uint32_t lane = lane_id();
   const uint64_t lane_bit = 1ull << lane;
 
-  // Uniform parameters of a single-set plan (scalar registers).
-  Slot<FP64> uni;
-  load_params(uni, a.sets[0]);
-  double gA_uni = 0.0;
-  if constexpr (!FP64) {
-    // one vector copy, so the per-block FP64 fma reads a single scalar pair
-    gA_uni = uni.p.gA;
-    asm volatile("" : "+v"(gA_uni));
+  // Constants of the set (of a single-set plan); gA also in one vector copy,
+  // so the per-block FP64 fma reads a single scalar pair.  Multi-set
+  // wavefronts load the constants of their lanes' set where they use them.
+  SetPar<FP64> P{};
+  double gA = 0.0;
+  if constexpr (!MULTI) {
+    P = load_setpar<FP64>(a.sets, 0);
+    if constexpr (!FP64) {
+      gA = P.p.gA;
+      asm volatile("" : "+v"(gA));
+    }
   }
+  const uint64_t jmax_one = MULTI ? 0ull : ((ConstSetDev*)a.sets)[0].jmax;
 
   Slot<FP64> s[R];
   // activity of each slot as a wavefront mask, and the number of blocks all
@@ -419,7 +642,6 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
   for (int r = 0; r < R; ++r) {
     restore_slot(a, (uint64_t)r * a.n_lanes + lane_g, s[r]);
     const bool act = s[r].set != kInactive;
-    if (MULTI && act) load_params(s[r], a.sets[s[r].set]);
     if constexpr (MT) {
       const uint4 z4 = make_uint4(0, 0, 0, 0);
       mc[r] = MtCarry{z4, z4, z4, z4, 0u};
@@ -428,18 +650,21 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
                         (uint32_t)(s[r].j % kMtGroups));
     }
     amask[r] = __ballot(act);
-    safe[r] = blocks_to_cap(s[r], MULTI ? s[r].jmax : uni.jmax, act);
+    safe[r] = blocks_to_cap(s[r], slot_jmax<MULTI>(a, s[r], act, jmax_one), act);
   }
 
   bool starved = false;
   uint32_t blocks_run = 0;
+  // (counted in a vector register: the scalar ones set the resident waves)
+  uint32_t extra_passes = 0;
+  asm volatile("" : "+v"(extra_passes));
   for (int blk = 0; blk < a.blocks; ++blk) {
     // ---- refill free slots
     if (a.refill && !starved) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint64_t need = ~amask[r];
-        if (need) {
+        if (need && (!MULTI || !a.whole_waves || need == ~0ull)) {
           const uint32_t want = (uint32_t)__popcll(need);
           const int leader = __ffsll((unsigned long long)need) - 1;
           unsigned long long base = 0;
@@ -456,7 +681,6 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
             if (rk < got && map_flat(a, base + rk, &set, &idx)) {
               const SetDev& sd = a.sets[set];
               start_replica(s[r], set, idx, sd);
-              if (MULTI) load_params(s[r], sd);
               if constexpr (MT) {
                 const uint64_t slot = (uint64_t)r * a.n_lanes + lane_g;
                 mt_seed_slot(a.st_mt, n_slots, slot, mt_replica_seed(sd.seed, idx));
@@ -468,8 +692,8 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
           const uint64_t newly = __ballot(assigned);
           if (newly) {
             amask[r] |= newly;
-            safe[r] = blocks_to_cap(s[r], MULTI ? s[r].jmax : uni.jmax,
-                                    (amask[r] & lane_bit) != 0);
+            const bool act = (amask[r] & lane_bit) != 0;
+            safe[r] = blocks_to_cap(s[r], slot_jmax<MULTI>(a, s[r], act, jmax_one), act);
           }
         }
       }
@@ -480,140 +704,116 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
     if (any == 0) break;
     ++blocks_run;
 
-    // ---- 4 Euler steps per slot
-    uint64_t esc[R][4];
-    const uint32_t key0 = uni.k0, key1 = uni.k1;
-    if constexpr (FP64) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        Slot<FP64>& sl = s[r];
-        const auto& p = MULTI ? sl.p : uni.p;
-        const Words w = block_words<MT, !MULTI>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
-                                        (amask[r] & lane_bit) != 0, mc[r], sl,
-                                        MULTI ? sl.k0 : key0, MULTI ? sl.k1 : key1);
-        double z[4];
-        normals_f64(w, z);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double kd = sl.kd + (double)q;
-          if constexpr (MODEL == kUnderExplicit) {
-            step_f64_under(p, kd, z[q], sl.phi, sl.v);
-          } else if constexpr (MODEL == kUnderSemiImplicit) {
-            step_f64_under_si(p, kd, z[q], sl.phi, sl.v);
-          } else {
-            step_f64_over(p, kd, z[q], sl.phi);
+    if constexpr (MULTI && R == 1) {
+      // Wavefronts that refill only when free in every lane: while all active
+      // lanes hold one set, run blocks with that set's constants fixed (the
+      // single-set loop) until the wavefront is empty or the launch ends.
+      if (a.whole_waves) {
+        const uint32_t s_first = (uint32_t)__builtin_amdgcn_readlane(
+            (int)s[0].set, __ffsll((unsigned long long)amask[0]) - 1);
+        if ((__ballot(s[0].set != s_first) & amask[0]) == 0) {
+          const SetPar<FP64> Q = load_setpar<FP64>(a.sets, s_first);
+          double gQ = 0.0;
+          if constexpr (!FP64) {
+            gQ = Q.p.gA;
+            asm volatile("" : "+v"(gQ));
           }
-          esc[r][q] = __ballot(sl.phi > p.th);
+          for (;;) {
+            uint64_t e1[1][4];
+            if constexpr (FP64) {
+              block_f64<MODEL, 1, MT, false>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, Q,
+                                             nullptr, e1);
+            } else {
+              float ph_q[1][5], y_q[1][4];
+              block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, Q, gQ,
+                                      ph_q, y_q);
+              threshold_f32(ph_q[0], y_q[0], Q.p.th_near_rev, Q.p.th_rev, amask[0], e1[0]);
+            }
+            finish_slot<false>(tab, a, s[0], amask[0], safe[0], e1[0], lane_bit, kInactive);
+            if (amask[0] == 0 || blk + 1 >= a.blocks) break;
+            ++blk;
+            ++blocks_run;
+          }
+          continue;
         }
+      }
+    }
+
+    // ---- 4 Euler steps per slot, then the threshold test
+    uint64_t esc[R][4];
+    if constexpr (!MULTI) {
+      if constexpr (FP64) {
+        block_f64<MODEL, R, MT, false>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, P,
+                                       nullptr, esc);
+      } else {
+        float ph_q[R][5], y_q[R][4];
+        block_f32<MODEL, R, MT>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, P, gA, ph_q,
+                                y_q);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          threshold_f32(ph_q[r], y_q[r], P.p.th_near_rev, P.p.th_rev, amask[r], esc[r]);
       }
     } else {
-      // generator and normals of every slot first, then the 4 steps with the
-      // slots interleaved (independent chains for the scheduler)
-      BoxMullerF32 bm[R];
-      BlockG gk[R];
-      float zs[R][2];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        Slot<FP64>& sl = s[r];
-        const auto& p = MULTI ? sl.p : uni.p;
-        const Words w = block_words<MT, !MULTI>(a, n_slots, (uint64_t)r * a.n_lanes + lane_g,
-                                        (amask[r] & lane_bit) != 0, mc[r], sl,
-                                        MULTI ? sl.k0 : key0, MULTI ? sl.k1 : key1);
-        bm[r] = box_muller_f32(w);
-        gk[r] = block_g4(p, sl.kd, MULTI ? p.gA : gA_uni);
-        // all four bias terms exist before the first step, so every step can
-        // accumulate into its own (the first otherwise still feeds the rest)
-        asm volatile("" : "+v"(gk[r].g[0]), "+v"(gk[r].g[1]), "+v"(gk[r].g[2]),
-                     "+v"(gk[r].g[3]));
-        zs[r][0] = p.sig * bm[r].radius[0];
-        zs[r][1] = p.sig * bm[r].radius[1];
-      }
-      // phases after each step and the compensated increments y (the error
-      // terms are recomputed from them only in the rare exact test)
-      float ph_q[R][5], y_q[R][4];
-#pragma unroll
-      for (int r = 0; r < R; ++r) ph_q[r][0] = s[r].phi;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          Slot<FP64>& sl = s[r];
-          const auto& p = MULTI ? sl.p : uni.p;
-          const float trig = (q & 1) ? bm[r].s[q >> 1] : bm[r].c[q >> 1];
-          if constexpr (MODEL == kUnderExplicit) {
-            y_q[r][q] = step_f32_under(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e, sl.v);
-          } else if constexpr (MODEL == kUnderSemiImplicit) {
-            y_q[r][q] =
-                step_f32_under_si(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e, sl.v);
+        // the set of the first active lane; one pass at full width when every
+        // active lane has it, else one pass per set
+        const uint64_t todo0 = amask[r];
+        const uint32_t s_first =
+            todo0 ? (uint32_t)__builtin_amdgcn_readlane(
+                        (int)s[r].set, __ffsll((unsigned long long)todo0) - 1)
+                  : 0u;
+        // (one-slot kernels reach this point with mixed wavefronts, or
+        // without whole-wavefront refill: passes only, one body less)
+        if (R > 1 && (__ballot(s[r].set != s_first) & todo0) == 0) {
+          const SetPar<FP64> Q = load_setpar<FP64>(a.sets, s_first);
+          if constexpr (FP64) {
+            block_f64<MODEL, 1, MT, false>(a, n_slots, lane_g, lane_bit, r, &amask[r], &mc[r],
+                                           &s[r], Q, nullptr, &esc[r]);
           } else {
-            y_q[r][q] = step_f32_over(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e);
+            double gQ = Q.p.gA;
+            asm volatile("" : "+v"(gQ));
+            float ph_q[5], y_q[4];
+            block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, r, &amask[r], &mc[r], &s[r],
+                                    Q, gQ, &ph_q, &y_q);
+            threshold_f32(ph_q, y_q, Q.p.th_near_rev, Q.p.th_rev, amask[r], esc[r]);
           }
-          ph_q[r][q + 1] = sl.phi;
-        }
-      }
-      // one compare per slot and block on the largest phase; the exact FP64
-      // test of each step only where a lane came near the threshold
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const auto& p = MULTI ? s[r].p : uni.p;
-        esc[r][0] = esc[r][1] = esc[r][2] = esc[r][3] = 0ull;
-        const float top = fmaxf(fmaxf(ph_q[r][1], ph_q[r][2]), fmaxf(ph_q[r][3], ph_q[r][4]));
-        // (active lanes only: a finished lane keeps its last phase until it
-        // takes a new replica)
-        if (__ballot(top > p.th_near_rev) & amask[r]) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float ph = ph_q[r][q + 1];
-            // opaque copy: the error term is recomputed here, not kept live
-            // from the step (which would block the accumulate form there)
-            float y = y_q[r][q];
-            asm volatile("" : "+v"(y));
-            esc[r][q] = __ballot(ph > p.th_near_rev &&
-                                 above_f64(ph, kahan_error(y, ph, ph_q[r][q]), p.th_rev));
+        } else {
+          // a lane is in the pass of set s0 exactly when its set is s0 (a
+          // free lane's set is kInactive); each pass tests its own lanes
+          // against its set's threshold and leaves per-lane escape bits
+          uint32_t bits = 0;
+          for (uint64_t todo = todo0; todo;) {
+            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane(
+                (int)s[r].set, __ffsll((unsigned long long)todo) - 1);
+            const bool mine = s[r].set == s0;
+            todo &= ~__ballot(mine);
+            const SetPar<FP64> Q = load_setpar<FP64>(a.sets, s0);
+            if (mine) {
+              if constexpr (FP64) {
+                block_f64<MODEL, 1, MT, true>(a, n_slots, lane_g, lane_bit, r, &amask[r],
+                                              &mc[r], &s[r], Q, &bits, nullptr);
+              } else {
+                double gQ = Q.p.gA;
+                asm volatile("" : "+v"(gQ));
+                float ph_q[5], y_q[4];
+                block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, r, &amask[r], &mc[r],
+                                        &s[r], Q, gQ, &ph_q, &y_q);
+                bits = threshold_bits_f32(ph_q, y_q, Q.p.th_near_rev, Q.p.th_rev);
+              }
+            }
+            if (todo) ++extra_passes;
           }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) esc[r][q] = __ballot((bits >> q) & 1u);
         }
       }
     }
 
     // ---- escapes, censoring, next block
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      Slot<FP64>& sl = s[r];
-      const uint64_t jmax = MULTI ? sl.jmax : uni.jmax;
-      const uint64_t crossed = (esc[r][0] | esc[r][1] | esc[r][2] | esc[r][3]) & amask[r];
-      const bool check_cap = safe[r] == 0;
-      const uint64_t last = check_cap ? (__ballot(sl.j >= jmax) & amask[r]) : 0ull;
-      if (crossed | last) {
-        bool fin = false;
-        int64_t k = -1;
-        if ((crossed | last) & lane_bit) {
-          int q1 = 0;
-          if (esc[r][0] & lane_bit) q1 = 1;
-          else if (esc[r][1] & lane_bit) q1 = 2;
-          else if (esc[r][2] & lane_bit) q1 = 3;
-          else if (esc[r][3] & lane_bit) q1 = 4;
-          const int64_t kesc = q1 ? (int64_t)(4 * sl.j) + q1 : 0;
-          const int64_t max_steps = a.sets[MULTI ? sl.set : 0].max_steps;
-          if (q1 && kesc <= max_steps) {
-            fin = true;
-            k = kesc;
-          } else if (sl.j >= jmax) {
-            fin = true;
-            k = -1;
-          }
-        }
-        record_finished(tab, a, fin, sl.set, sl.idx, k);
-        if (fin) sl.set = kInactive;
-        amask[r] &= ~__ballot(fin);
-      }
-      sl.j += 1;
-      sl.kd += 4.0;
-      if (check_cap) {
-        safe[r] = blocks_to_cap(sl, jmax, (amask[r] & lane_bit) != 0);
-      } else {
-        --safe[r];
-      }
-    }
+    for (int r = 0; r < R; ++r)
+      finish_slot<MULTI>(tab, a, s[r], amask[r], safe[r], esc[r], lane_bit, 0u);
   }
 
   // ---- leave state resident, count issued lane-steps
@@ -622,6 +822,8 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
   if (lane == 0 && blocks_run)
     atomicAdd(&a.ctr->lane_steps,
               (unsigned long long)blocks_run * (unsigned long long)(kWave * R * 4));
+  if (MULTI && lane == 0 && extra_passes)
+    atomicAdd(&a.ctr->extra_passes, (unsigned long long)extra_passes);
 
   // ---- one global pass over the workgroup's LDS tables
   __syncthreads();
@@ -646,6 +848,11 @@ __global__ __launch_bounds__(kBlockThreads) void slice_kernel(SliceArgs a) {
     if (v[4] | v[5]) atomic_add_u128(&m->sum_k2_lo, &m->sum_k2_hi, v[4], v[5]);
     if (v[0] + v[1]) atomicAdd(&a.ctr->done, v[0] + v[1]);
   }
+}
+
+template <bool FP64, int MODEL, int R, bool MULTI, bool MT>
+__global__ __launch_bounds__(kBlockThreads, (MULTI && !FP64 && R == 1) ? 8 : 1) void slice_kernel(SliceArgs a) {
+  slice_body<FP64, MODEL, R, MULTI, MT>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -717,6 +924,137 @@ __global__ __launch_bounds__(kBlockThreads) void compact_move_kernel(SliceArgs s
   dst.st_v[pos] = src.st_v[slot];
 }
 
+// ---------------------------------------------------------------------------
+// Grouping by set: the active slots' state moves to another state buffer in
+// the order of their sets, so the lanes of a wavefront share a set and a
+// multi-set block takes one pass.  Counting per set, an exclusive scan into
+// first positions, then the move, which claims positions within its set.
+
+// Wavefront-aggregated claim of the next position of counter[key] by each
+// flagged lane: one atomic per distinct key among the lanes.
+__device__ __forceinline__ uint64_t claim_by_key(unsigned long long* counter, uint32_t key,
+                                                 bool flag) {
+  const uint64_t lane_bit = 1ull << lane_id();
+  uint64_t pending = __ballot(flag);
+  uint64_t pos = 0;
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t lkey = __builtin_amdgcn_readlane((int)key, leader);
+    const uint64_t same = __ballot(flag && key == lkey) & pending;
+    unsigned long long base = 0;
+    if (lane_id() == (uint32_t)leader)
+      base = atomicAdd(&counter[lkey], (unsigned long long)__popcll(same));
+    base = read_lane_u64(base, leader);
+    if (same & lane_bit) pos = base + rank_in(same);
+    pending &= ~same;
+  }
+  return pos;
+}
+
+// counts[set] += active slots of the set (counts zeroed before).
+__global__ __launch_bounds__(kBlockThreads) void group_count_kernel(SliceArgs a,
+                                                                    uint64_t n_slots,
+                                                                    unsigned long long* counts) {
+  const uint64_t slot = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  const uint32_t set = slot < n_slots ? a.st_set[slot] : kInactive;
+  (void)claim_by_key(counts, set, set != kInactive);
+}
+
+// Exclusive prefix sum of counts[0, n) in place, by one workgroup, each
+// count rounded up to a multiple of `align` (64: every set's slots start a
+// wavefront, so none holds two sets); the total goes to ctr->compact.
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void group_scan_kernel(unsigned long long* counts,
+                                                                  uint64_t n, uint32_t align,
+                                                                  Counters* ctr) {
+  __shared__ unsigned long long part[kScanThreads];
+  const uint64_t per = (n + kScanThreads - 1) / kScanThreads;
+  const uint64_t b = (uint64_t)threadIdx.x * per;
+  const uint64_t e = b + per < n ? b + per : n;
+  const unsigned long long m = align - 1;
+  unsigned long long sum = 0;
+  for (uint64_t i = b; i < e; ++i) sum += (counts[i] + m) & ~m;
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int i = 0; i < kScanThreads; ++i) {
+      const unsigned long long v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    ctr->compact = run;
+  }
+  __syncthreads();
+  unsigned long long run = part[threadIdx.x];
+  for (uint64_t i = b; i < e; ++i) {
+    const unsigned long long v = (counts[i] + m) & ~m;
+    counts[i] = run;
+    run += v;
+  }
+}
+
+// Moves each active slot to the next position of its set (first[] from the
+// scan); dst's set array must already mark every slot inactive.
+__global__ __launch_bounds__(kBlockThreads) void group_move_kernel(SliceArgs src, SliceArgs dst,
+                                                                   uint64_t n_slots,
+                                                                   unsigned long long* first) {
+  const uint64_t slot = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  const uint32_t set = slot < n_slots ? src.st_set[slot] : kInactive;
+  const bool act = set != kInactive;
+  const uint64_t pos = claim_by_key(first, set, act);
+  if (!act) return;
+  dst.st_set[pos] = set;
+  dst.st_idx[pos] = src.st_idx[slot];
+  dst.st_j[pos] = src.st_j[slot];
+  dst.st_phi[pos] = src.st_phi[slot];
+  dst.st_v[pos] = src.st_v[slot];
+}
+
+// After a move in set order (the sets' wavefront-aligned slots fill
+// [0, ctr->compact)), the free slots past them take the next undrawn replicas
+// in queue order.  The cursor stays a multiple of 64 (so does every draw of a
+// whole wavefront), so each new wavefront holds one work-queue chunk: one set.
+template <bool FP64>
+__global__ __launch_bounds__(kBlockThreads) void group_refill_kernel(SliceArgs a,
+                                                                     uint64_t n_slots) {
+  const uint64_t pos = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  const uint64_t active = a.ctr->compact;
+  const uint64_t cursor = a.ctr->cursor;
+  if (pos >= n_slots || pos < active || cursor >= a.total) return;
+  const uint64_t flat = cursor + (pos - active);
+  uint32_t set;
+  uint64_t idx;
+  if (flat >= a.total || !map_flat(a, flat, &set, &idx)) return;
+  Slot<FP64> s;
+  start_replica(s, set, idx, a.sets[set]);
+  store_slot(a, pos, s);
+}
+
+// The cursor past the replicas the refill took (never past `total`).
+__global__ void group_advance_kernel(Counters* ctr, uint64_t n_slots,
+                                     unsigned long long total) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const unsigned long long active = ctr->compact;
+  const unsigned long long cursor = ctr->cursor;
+  if (cursor >= total) return;
+  const unsigned long long free = active < n_slots ? n_slots - active : 0ull;
+  ctr->cursor = cursor + (free < total - cursor ? free : total - cursor);
+}
+
+// Lane state of n_slots slots from src to dst.
+__global__ __launch_bounds__(kBlockThreads) void copy_state_kernel(SliceArgs src, SliceArgs dst,
+                                                                   uint64_t n_slots) {
+  const uint64_t slot = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  if (slot >= n_slots) return;
+  dst.st_set[slot] = src.st_set[slot];
+  dst.st_idx[slot] = src.st_idx[slot];
+  dst.st_j[slot] = src.st_j[slot];
+  dst.st_phi[slot] = src.st_phi[slot];
+  dst.st_v[slot] = src.st_v[slot];
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t value) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = value;
@@ -786,7 +1124,12 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Slot<FP64> s;
   start_replica(s, 0, replica, sd);
-  load_params(s, sd);
+  SetPar<FP64> P;
+  if constexpr (FP64) {
+    P.p = load_par_f64(sd);
+  } else {
+    P.p = load_par_f32(sd);
+  }
   MtCarry mc{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0),
              make_uint4(0, 0, 0, 0), 0u};
   if (mt) {
@@ -801,27 +1144,27 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
       for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
         const double kd = s.kd + (double)q;
         if constexpr (MODEL == kUnderExplicit) {
-          step_f64_under(s.p, kd, z[q], s.phi, s.v);
+          step_f64_under(P.p, kd, z[q], s.phi, s.v);
         } else if constexpr (MODEL == kUnderSemiImplicit) {
-          step_f64_under_si(s.p, kd, z[q], s.phi, s.v);
+          step_f64_under_si(P.p, kd, z[q], s.phi, s.v);
         } else {
-          step_f64_over(s.p, kd, z[q], s.phi);
+          step_f64_over(P.p, kd, z[q], s.phi);
         }
         out_phi[k0 + q] = s.phi;
         out_v[k0 + q] = s.v;
       }
     } else {
       const BoxMullerF32 bm = box_muller_f32(w);
-      const BlockG gk = block_g4(s.p, s.kd, s.p.gA);
+      const BlockG gk = block_g4(P.p, s.kd, P.p.gA);
       for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
-        const float zs = s.p.sig * bm.radius[q >> 1];
+        const float zs = P.p.sig * bm.radius[q >> 1];
         const float trig = (q & 1) ? bm.s[q >> 1] : bm.c[q >> 1];
         if constexpr (MODEL == kUnderExplicit) {
-          step_f32_under(s.p, gk.g[q], zs, trig, s.phi, s.e, s.v);
+          step_f32_under(P.p, gk.g[q], zs, trig, s.phi, s.e, s.v);
         } else if constexpr (MODEL == kUnderSemiImplicit) {
-          step_f32_under_si(s.p, gk.g[q], zs, trig, s.phi, s.e, s.v);
+          step_f32_under_si(P.p, gk.g[q], zs, trig, s.phi, s.e, s.v);
         } else {
-          step_f32_over(s.p, gk.g[q], zs, trig, s.phi, s.e);
+          step_f32_over(P.p, gk.g[q], zs, trig, s.phi, s.e);
         }
         out_phi[k0 + q] = 2.0 * kPi * ((double)s.phi + (double)s.e);
         out_v[k0 + q] = (double)s.v;
@@ -919,6 +1262,64 @@ hipError_t launch_compact_move(const SliceArgs& src, const SliceArgs& dst, uint6
   }
   if (n_slots == 0) return hipSuccess;
   hipLaunchKernelGGL(compact_move_kernel,
+                     dim3((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads)),
+                     dim3(kBlockThreads), 0, st, src, dst, n_slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_count(const SliceArgs& a, uint64_t n_slots, unsigned long long* counts,
+                              uint64_t n_sets, hipStream_t st) {
+  if (n_sets == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((uint32_t)((n_sets + 255) / 256)), dim3(256), 0, st,
+                     counts, n_sets, 0ull);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (n_slots > 0) {
+    hipLaunchKernelGGL(group_count_kernel,
+                       dim3((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads)),
+                       dim3(kBlockThreads), 0, st, a, n_slots, counts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, counts, n_sets,
+                     (uint32_t)kWave, a.ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_move(const SliceArgs& src, const SliceArgs& dst, uint64_t n_slots,
+                             uint64_t n_dst_slots, unsigned long long* first, hipStream_t st) {
+  if (n_dst_slots > 0) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((uint32_t)((n_dst_slots + 255) / 256)), dim3(256),
+                       0, st, dst.st_set, n_dst_slots, kInactive);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (n_slots == 0) return hipSuccess;
+  hipLaunchKernelGGL(group_move_kernel,
+                     dim3((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads)),
+                     dim3(kBlockThreads), 0, st, src, dst, n_slots, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_refill(bool fp64, const SliceArgs& a, uint64_t n_slots,
+                               hipStream_t st) {
+  if (n_slots == 0) return hipSuccess;
+  const dim3 g((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads));
+  if (fp64) {
+    hipLaunchKernelGGL(group_refill_kernel<true>, g, dim3(kBlockThreads), 0, st, a, n_slots);
+  } else {
+    hipLaunchKernelGGL(group_refill_kernel<false>, g, dim3(kBlockThreads), 0, st, a, n_slots);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(group_advance_kernel, dim3(1), dim3(64), 0, st, a.ctr, n_slots, a.total);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_state(const SliceArgs& src, const SliceArgs& dst, uint64_t n_slots,
+                             hipStream_t st) {
+  if (n_slots == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_state_kernel,
                      dim3((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads)),
                      dim3(kBlockThreads), 0, st, src, dst, n_slots);
   return hipGetLastError();

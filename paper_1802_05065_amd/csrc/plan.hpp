@@ -38,6 +38,7 @@ struct Plan {
   // second lane-state buffer for tail compaction (refill plans without MT)
   uint64_t off_alt_phi = 0, off_alt_v = 0, off_alt_j = 0, off_alt_idx = 0, off_alt_set = 0;
   bool has_alt = false;
+  uint64_t off_group = 0;       // per-set positions of a regrouping (multi-set)
   uint64_t ws_bytes = 0;
 
   // last run
@@ -59,10 +60,17 @@ struct Plan {
   SliceArgs slice_args(char* ws, uint64_t* hist, uint64_t n_lanes, int buf = 0) const;
   fpt_status maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes, int R,
                            hipStream_t st, bool* compacted);
+  fpt_status enqueue_regroup(char* ws, const SliceArgs& a, int buf, uint64_t lanes, int R,
+                             hipStream_t st);
   bool tail_launches(SliceArgs& a, uint64_t slots, uint64_t draw_per_group);
   bool tail_mode = false;
   uint64_t last_cursor = 0;     // cursor at the previous check
   uint64_t lanes_for(const fpt_tuning& t) const;
+  // multi-set refill runs sort by set and refill between launches, and
+  // refill only whole wavefronts inside one
+  bool regroups(const fpt_tuning& t) const {
+    return multi && has_alt && t.schedule == FPT_SCHED_REFILL && !t.no_regroup;
+  }
   int resident_waves(int R) const;
   uint64_t launch_bound(uint64_t n_slots, int blocks) const;
   fpt_status ensure_host_resources(size_t n_events);

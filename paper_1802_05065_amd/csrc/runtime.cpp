@@ -222,6 +222,8 @@ fpt_status Plan::layout() {
     off = align256(off + 8 * slots);
     off_alt_set = off;
     off = align256(off + 4 * slots);
+    off_group = off;
+    if (multi) off = align256(off + sizeof(unsigned long long) * sets.size());
   }
   ws_bytes = off;
   return FPT_OK;
@@ -348,11 +350,13 @@ bool Plan::tail_launches(SliceArgs& a, uint64_t slots, uint64_t draw_per_group) 
 // Tail compaction between launches (the counters in h_ctr are current): when
 // no undrawn replica is left and the active ones fill at most 80% of the
 // slots, count them, and if the launch can narrow by a tenth or more, move
-// their state to a dense prefix of the other state buffer.  (Thresholds
-// from a sweep on the uneven and batched workloads: 50%/25% left 8% of the
-// batched run's lane-steps idle, 80%/10% leaves 3%.)
+// their state to a dense prefix of the other state buffer (in set order for
+// multi-set plans).  (Thresholds from a sweep on the uneven and batched
+// workloads: 50%/25% left 8% of the batched run's lane-steps idle, 80%/10%
+// leaves 3%.)
 constexpr uint64_t kCompactTriggerPercent = 80;
 constexpr uint64_t kCompactNarrowPercent = 90;
+
 fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes, int R,
                                hipStream_t st, bool* compacted) {
   *compacted = false;
@@ -362,8 +366,13 @@ fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes
   const uint64_t done = (uint64_t)h_ctr->done;
   const uint64_t active_bound = total_flat - std::min<uint64_t>(done, total_flat);
   if (active_bound * 100 > slots * kCompactTriggerPercent) return FPT_OK;
+  auto* first = reinterpret_cast<unsigned long long*>(ws + off_group);
   FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, st));
-  FPT_HIP(launch_compact_count(a, slots, st));
+  if (multi) {
+    FPT_HIP(launch_group_count(a, slots, first, sets.size(), st));
+  } else {
+    FPT_HIP(launch_compact_count(a, slots, st));
+  }
   FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   FPT_HIP(hipStreamSynchronize(st));
   const uint64_t active = h_ctr->compact;
@@ -374,8 +383,13 @@ fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes
   dst.blocks = a.blocks;
   dst.refill = a.refill;
   dst.clamp = a.clamp;
-  FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, st));
-  FPT_HIP(launch_compact_move(a, dst, slots, new_lanes * (uint64_t)R, st));
+  dst.whole_waves = a.whole_waves;
+  if (multi) {
+    FPT_HIP(launch_group_move(a, dst, slots, new_lanes * (uint64_t)R, first, st));
+  } else {
+    FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, st));
+    FPT_HIP(launch_compact_move(a, dst, slots, new_lanes * (uint64_t)R, st));
+  }
   if (verbose())
     std::fprintf(stderr, "[fpt] compaction: %llu active slots, %llu -> %llu lanes\n",
                  (unsigned long long)active, (unsigned long long)lanes,
@@ -385,6 +399,24 @@ fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes
   lanes = new_lanes;
   ++stats.n_compactions;
   *compacted = true;
+  return FPT_OK;
+}
+
+// Multi-set refill runs, after every launch while undrawn replicas are left:
+// the active slots move into set order through the other state buffer, the
+// free slots past them take the next replicas in queue order, and the state
+// comes back, so wavefronts hold one set again (inside a launch only
+// wavefronts free in every lane draw new replicas).  Six small kernels, no
+// host synchronization, so a captured group of launches includes them.
+fpt_status Plan::enqueue_regroup(char* ws, const SliceArgs& a, int buf, uint64_t lanes, int R,
+                                 hipStream_t st) {
+  const uint64_t slots = lanes * (uint64_t)R;
+  const SliceArgs other = slice_args(ws, reinterpret_cast<uint64_t*>(a.hist), lanes, 1 - buf);
+  auto* first = reinterpret_cast<unsigned long long*>(ws + off_group);
+  FPT_HIP(launch_group_count(a, slots, first, sets.size(), st));
+  FPT_HIP(launch_group_move(a, other, slots, slots, first, st));
+  FPT_HIP(launch_group_refill(precision == FPT_FP64, other, slots, st));
+  FPT_HIP(launch_copy_state(other, a, slots, st));
   return FPT_OK;
 }
 
@@ -415,9 +447,12 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
     table[i].out_steps = out_steps ? out_steps[i] : nullptr;
   FPT_TRY(upload_sets(ws, table, st));
 
+  // multi-set refill runs keep wavefronts to one set (enqueue_regroup)
+  const bool regroup = regroups(tuning);
   SliceArgs a = slice_args(ws, hist_dev, n_lanes);
   a.blocks = blocks;
   a.refill = refill ? 1 : 0;
+  a.whole_waves = regroup ? 1 : 0;
   FPT_TRY(reset_run(a, n_lanes, R, refill, st));
 
   uint64_t lanes = n_lanes;  // narrows at each tail compaction
@@ -448,17 +483,23 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
     if (!graph_stream) FPT_HIP(hipStreamCreateWithFlags(&graph_stream, hipStreamNonBlocking));
     FPT_HIP(hipEventRecord(events[2], st));
     FPT_HIP(hipStreamWaitEvent(graph_stream, events[2], 0));
+    bool graph_regroup = false;  // the captured group regroups after each launch
     auto capture = [&]() -> fpt_status {
       if (graph_exec) {
         (void)hipGraphExecDestroy(graph_exec);
         graph_exec = nullptr;
       }
+      graph_regroup = regroup && last_cursor < total_flat;
       const uint32_t groups = (uint32_t)(lanes / kBlockThreads);
       hipGraph_t g = nullptr;
       FPT_HIP(hipStreamBeginCapture(graph_stream, hipStreamCaptureModeThreadLocal));
       hipError_t cap_err = hipSuccess;
-      for (int i = 0; i < group && cap_err == hipSuccess; ++i)
+      for (int i = 0; i < group && cap_err == hipSuccess; ++i) {
         cap_err = launch_slice(fp64, model, R, multi, a, groups, graph_stream);
+        if (cap_err == hipSuccess && graph_regroup &&
+            enqueue_regroup(ws, a, buf, lanes, R, graph_stream) != FPT_OK)
+          cap_err = hipErrorUnknown;
+      }
       if (cap_err == hipSuccess)
         cap_err = hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
                                  graph_stream);
@@ -484,6 +525,7 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       FPT_HIP(hipEventElapsedTime(&ms, events[0], events[1]));
       kernel_ms += ms;
       launches += group;
+      if (graph_regroup) stats.n_regroups += group;
       blocks_issued += (uint64_t)group * (uint64_t)a.blocks;
       finished = h_ctr->done >= total_replicas;
       if (!finished && blocks_issued > bound_blocks)
@@ -496,7 +538,8 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
         FPT_TRY(maybe_compact(ws, a, buf, lanes, R, graph_stream, &compacted));
         const bool shorter = tail_launches(a, lanes * (uint64_t)R, advance);
         if (shorter) group = 1;
-        if (compacted || shorter) FPT_TRY(capture());
+        const bool drained = graph_regroup && last_cursor >= total_flat;
+        if (compacted || shorter || drained) FPT_TRY(capture());
       }
     }
     FPT_HIP(hipEventRecord(events[3], graph_stream));
@@ -505,12 +548,17 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
     while (!finished) {
       FPT_TRY(ensure_host_resources(ev_used + 2 * group + 1));
       const uint32_t groups = (uint32_t)(lanes / kBlockThreads);
+      const bool regroup_now = regroup && last_cursor < total_flat;
       for (int i = 0; i < group; ++i) {
         hipEvent_t e0 = events[ev_used++], e1 = events[ev_used++];
         FPT_HIP(hipEventRecord(e0, st));
         FPT_HIP(launch_slice(fp64, model, R, multi, a, groups, st));
         FPT_HIP(hipEventRecord(e1, st));
         marks.emplace_back(e0, e1);
+        if (regroup_now) {
+          FPT_TRY(enqueue_regroup(ws, a, buf, lanes, R, st));
+          ++stats.n_regroups;
+        }
         ++launches;
         blocks_issued += (uint64_t)a.blocks;
       }
@@ -543,7 +591,10 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
     }
   }
   if (total_replicas == 0) FPT_TRY(ensure_host_resources(1));
-  if (total_replicas > 0) stats.lane_steps = h_ctr->lane_steps;
+  if (total_replicas > 0) {
+    stats.lane_steps = h_ctr->lane_steps;
+    stats.extra_passes = h_ctr->extra_passes;
+  }
   stats.n_launches = launches;
   stats.kernel_ms = kernel_ms;
   stats.wall_ms =

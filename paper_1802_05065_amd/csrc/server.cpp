@@ -116,6 +116,7 @@ struct Server {
   uint64_t off_alt[5] = {0, 0, 0, 0, 0};
   int buf = 0;
   uint64_t cur_lanes = 0;
+  uint64_t off_group = 0;      // per-set positions of a move in set order
   uint64_t off_hist = 0;
   RangeAlloc hist_alloc;
 
@@ -162,6 +163,7 @@ struct Server {
     a.blocks = tuning.steps_per_launch / 4;
     a.refill = 1;
     a.clamp = 1;
+    a.whole_waves = tuning.no_regroup ? 0 : 1;
     return a;
   }
 
@@ -215,6 +217,7 @@ fpt_status Server::setup() {
   off_alt[2] = take(8 * n_slots);
   off_alt[3] = take(8 * n_slots);
   off_alt[4] = take(4 * n_slots);
+  off_group = take(sizeof(unsigned long long) * kMaxSets);
   cur_lanes = n_lanes;
   if (off + sizeof(Chunk) * kMinRingChunks + 8 * FPT_MAX_BINS > pool_bytes)
     return fail(FPT_E_NOMEM, "pool of %zu bytes cannot hold the lane state (%llu bytes) "
@@ -321,15 +324,29 @@ void Server::finish_locked(Job* j, const MomDev& m) {
 // One launch over all admitted work, then retire finished jobs.
 fpt_status Server::step() {
   SliceArgs a;
+  int buf_seen = 0;
   {
     std::lock_guard<std::mutex> lk(mu);
     a = args();
+    buf_seen = buf;
   }
   const uint32_t groups = (uint32_t)(a.n_lanes / kBlockThreads);
   FPT_HIP(hipEventRecord(ev0, stream));
   FPT_HIP(launch_slice(precision == FPT_FP64, model, tuning.replicas_per_lane, true, a, groups,
                        stream));
   FPT_HIP(hipEventRecord(ev1, stream));
+  if (a.whole_waves && cursor_seen < a.total) {
+    // the active slots into set order, the free ones past them refilled in
+    // queue order (lanes of a wavefront share a set again)
+    const uint64_t slots = a.n_lanes * (uint64_t)tuning.replicas_per_lane;
+    const SliceArgs other = args_for(1 - buf_seen, a.n_lanes);
+    auto* first = reinterpret_cast<unsigned long long*>(pool + off_group);
+    FPT_HIP(launch_group_count(a, slots, first, kMaxSets, stream));
+    FPT_HIP(launch_group_move(a, other, slots, slots, first, stream));
+    FPT_HIP(launch_group_refill(precision == FPT_FP64, other, slots, stream));
+    FPT_HIP(launch_copy_state(other, a, slots, stream));
+    ++stats.n_regroups;
+  }
   FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
   FPT_HIP(hipMemcpyAsync(h_mom, a.mom, sizeof(MomDev) * kMaxSets, hipMemcpyDeviceToHost,
                          stream));
@@ -348,9 +365,9 @@ fpt_status Server::step() {
 }
 
 // With every appended replica drawn and the active ones filling at most 80%
-// of the current slots, move them to a dense prefix of the other lane-state
-// buffer (whose remaining slots, up to the full width, are marked free) and
-// narrow the launches; admit_locked widens them again.
+// of the current slots, move them in set order to a dense prefix of the other
+// lane-state buffer (whose remaining slots, up to the full width, are marked
+// free) and narrow the launches; admit_locked widens them again.
 fpt_status Server::maybe_compact_locked() {
   const uint64_t total = chunk_tail * kChunk;
   if (h_ctr->cursor < total || cur_lanes <= (uint64_t)kBlockThreads) return FPT_OK;
@@ -359,17 +376,16 @@ fpt_status Server::maybe_compact_locked() {
   const uint64_t active_bound = h_ctr->cursor - std::min<uint64_t>(h_ctr->cursor, h_ctr->done);
   if (active_bound * 10 > slots * 8) return FPT_OK;
   const SliceArgs a = args();
-  FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, stream));
-  FPT_HIP(launch_compact_count(a, slots, stream));
+  auto* first = reinterpret_cast<unsigned long long*>(pool + off_group);
+  FPT_HIP(launch_group_count(a, slots, first, kMaxSets, stream));
   FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
   FPT_HIP(hipStreamSynchronize(stream));
   const uint64_t active = h_ctr->compact;
-  const uint64_t lanes = std::max<uint64_t>(kBlockThreads,
-                                            round_up((active + R - 1) / R, kBlockThreads));
+  const uint64_t lanes =
+      std::max<uint64_t>(kBlockThreads, round_up((active + R - 1) / R, kBlockThreads));
   if (lanes * 10 > cur_lanes * 9) return FPT_OK;
   SliceArgs dst = args_for(1 - buf, lanes);
-  FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, stream));
-  FPT_HIP(launch_compact_move(a, dst, slots, n_slots, stream));
+  FPT_HIP(launch_group_move(a, dst, slots, n_slots, first, stream));
   FPT_HIP(hipStreamSynchronize(stream));
   buf = 1 - buf;
   cur_lanes = lanes;

@@ -212,6 +212,32 @@ def test_tail_compaction_keeps_results(prec):
         assert b0.counts[i].tolist() == b1.counts[i].tolist()
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_regrouping_keeps_results(prec):
+    # ramps over three decades: refilled lanes of a wavefront soon hold
+    # replicas of several sets, so blocks take extra passes until the active
+    # state is moved into set order; that move (and the passes) must not
+    # change any replica's result
+    sets = workloads.batched_sets(n_sets=32, seed=21, log2_min=13, log2_max=14,
+                                  ramp_scale=300.0)
+    t = dict(replicas_per_lane=1, waves_per_simd=1, steps_per_launch=4096)
+    ref = api.simulate(sets, prec, dict(t, no_regroup=1))
+    assert ref.stats["n_regroups"] == 0 and ref.stats["extra_passes"] > 0
+    for tt in (t, dict(t, use_graph=1),
+               dict(replicas_per_lane=2, waves_per_simd=1, steps_per_launch=2048)):
+        r = api.simulate(sets, prec, tt)
+        print(prec, tt, "regroups", r.stats["n_regroups"], "extra passes",
+              r.stats["extra_passes"], "vs", ref.stats["extra_passes"])
+        assert r.stats["n_regroups"] >= 1, tt
+        if tt["replicas_per_lane"] == 1:
+            assert r.stats["extra_passes"] < ref.stats["extra_passes"], tt
+        for i in range(len(sets)):
+            assert np.array_equal(_steps(r, i), _steps(ref, i)), (tt, i)
+            assert r.counts[i].tolist() == ref.counts[i].tolist(), (tt, i)
+            for k in INT_MOMENTS:
+                assert r.moments[i][k] == ref.moments[i][k], (tt, i, k)
+
+
 def test_uneven_overdamped_fp64_sample_matches_oracle():
     p = workloads.uneven_overdamped(n_replicas=2 ** 14, seed=3)
     gpu = _steps(api.simulate(p, "fp64", FIXED))
@@ -310,7 +336,8 @@ def test_serving_alone_equals_mix():
                 time.sleep(0.01)
         assert len(results) == len(jobs)
         st = _lib.fpt_server_stats_get(srv)
-        print(f"server: {st['n_launches']} launches, {st['n_compactions']} compactions")
+        print(f"server: {st['n_launches']} launches, {st['n_compactions']} compactions, "
+              f"{st['n_regroups']} regroups")
         assert st["finished"] == len(jobs)
         assert st["n_compactions"] >= 1
     finally:
