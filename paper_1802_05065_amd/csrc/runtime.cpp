@@ -655,6 +655,26 @@ fpt_status Plan::run_stats(fpt_run_stats* out) {
   return FPT_OK;
 }
 
+// Scheduling estimate of a replica's steps (only orders the work queue): a
+// ramped bias switches by the time it reaches 1, (1 - gamma0) / (ramp dt)
+// steps; a fixed bias below 1 escapes at the Kramers rate
+// omega / (2 pi) exp(-dU / T), omega = sqrt(V0) (1 - gamma^2)^(1/4) and
+// dU = 2 V0 (sqrt(1 - gamma^2) - gamma arccos gamma); at most max_steps.
+static double expected_steps(const fpt_params& q) {
+  const double cap = (double)q.max_steps;
+  const double dgamma = q.ramp * q.dt;
+  if (dgamma > 0.0) return std::min(cap, std::max(1.0, (1.0 - q.gamma0) / dgamma));
+  const double g = std::fabs(q.gamma0);
+  if (g >= 1.0 || q.T <= 0.0 || q.V0 <= 0.0) return cap;
+  const double c = std::sqrt(1.0 - g * g);
+  const double du = 2.0 * q.V0 * (c - g * std::acos(g));
+  const double omega = std::sqrt(q.V0) * std::sqrt(c);
+  const double expo = du / q.T;
+  if (expo > 700.0) return cap;
+  const double steps = 2.0 * M_PI * std::exp(expo) / (omega * q.dt);
+  return std::min(cap, std::max(1.0, steps));
+}
+
 fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision,
                      const fpt_tuning* tuning, Plan** out) {
   if (!params || n_sets < 1) return fail(FPT_E_INVAL, "need at least one parameter set");
@@ -702,7 +722,17 @@ fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision
   }
   p->hist_bins = off;
   if (p->multi) {
+    // the work queue takes the sets longest-expected first, so the replicas
+    // that set the end of the run start early (results do not depend on it)
+    std::vector<int32_t> order((size_t)n_sets);
+    std::vector<double> est((size_t)n_sets);
     for (int32_t i = 0; i < n_sets; ++i) {
+      order[(size_t)i] = i;
+      est[(size_t)i] = expected_steps(params[i]);
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return est[(size_t)x] > est[(size_t)y]; });
+    for (int32_t i : order) {
       const uint64_t n = (uint64_t)params[i].n_replicas;
       for (uint64_t first = 0; first < n; first += kChunk) {
         Chunk c;
