@@ -463,10 +463,12 @@ __device__ __forceinline__ void block_f32(const SliceArgs& a, uint64_t n_slots,
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     Slot<false>& sl = s[r];
+    // the bias terms first: independent of the generator, they fill its
+    // dependency chain
+    gk[r] = block_g4(p, sl.kd, gA);
     const Words w = block_words<MT>(a, n_slots, (uint64_t)(r0 + r) * a.n_lanes + lane_g,
                                     (amask[r] & lane_bit) != 0, mc[r], sl, P.k0, P.k1);
     bm[r] = box_muller_f32(w);
-    gk[r] = block_g4(p, sl.kd, gA);
     // all four bias terms exist before the first step, so every step can
     // accumulate into its own (the first otherwise still feeds the rest)
     asm volatile("" : "+v"(gk[r].g[0]), "+v"(gk[r].g[1]), "+v"(gk[r].g[2]),
@@ -929,6 +931,10 @@ __global__ __launch_bounds__(kBlockThreads) void compact_move_kernel(SliceArgs s
 // the order of their sets, so the lanes of a wavefront share a set and a
 // multi-set block takes one pass.  Counting per set, an exclusive scan into
 // first positions, then the move, which claims positions within its set.
+// Each workgroup takes a contiguous tile of slots (after the first regroup
+// they are in set order, so a tile holds few sets), sums per set in an LDS
+// table and makes one global atomic per set it holds; sets beyond the
+// table's capacity fall back to one atomic per wavefront.
 
 // Wavefront-aggregated claim of the next position of counter[key] by each
 // flagged lane: one atomic per distinct key among the lanes.
@@ -951,71 +957,186 @@ __device__ __forceinline__ uint64_t claim_by_key(unsigned long long* counter, ui
   return pos;
 }
 
-// counts[set] += active slots of the set (counts zeroed before).
+constexpr int kGroupPerThread = 8;                               // slots per thread
+constexpr int kGroupTile = kBlockThreads * kGroupPerThread;      // slots per workgroup
+constexpr int kGroupTable = 128;                                 // LDS entries (sets)
+constexpr uint32_t kNoEntry = 0xFFFFFFFFu;
+
+struct GroupTable {
+  uint32_t key[kGroupTable];
+  uint32_t cnt[kGroupTable];
+  unsigned long long base[kGroupTable];
+};
+
+__device__ __forceinline__ void group_table_init(GroupTable& t) {
+  for (int i = threadIdx.x; i < kGroupTable; i += kBlockThreads) {
+    t.key[i] = kEmpty;
+    t.cnt[i] = 0;
+  }
+}
+
+// Adds the wavefront's flagged lanes to the table, one LDS atomic per
+// distinct set; returns this lane's entry (kNoEntry: table full, or unflagged).
+__device__ __forceinline__ uint32_t group_table_add(GroupTable& t, uint32_t set, bool flag) {
+  uint64_t pending = __ballot(flag);
+  uint32_t entry = kNoEntry;
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t lset = (uint32_t)__builtin_amdgcn_readlane((int)set, leader);
+    const uint64_t same = __ballot(flag && set == lset) & pending;
+    uint32_t e = kNoEntry;
+    if (lane_id() == (uint32_t)leader) {
+      uint32_t h = hash32(lset) & (kGroupTable - 1);
+      for (int probe = 0; probe < kGroupTable; ++probe) {
+        const uint32_t prev = atomicCAS(&t.key[h], kEmpty, lset);
+        if (prev == kEmpty || prev == lset) {
+          atomicAdd(&t.cnt[h], (uint32_t)__popcll(same));
+          e = h;
+          break;
+        }
+        h = (h + 1) & (kGroupTable - 1);
+      }
+    }
+    e = (uint32_t)__builtin_amdgcn_readlane((int)e, leader);
+    if (same & (1ull << lane_id())) entry = e;
+    pending &= ~same;
+  }
+  return entry;
+}
+
+// counts[set] += active slots of the set (counts are zero before).
 __global__ __launch_bounds__(kBlockThreads) void group_count_kernel(SliceArgs a,
                                                                     uint64_t n_slots,
                                                                     unsigned long long* counts) {
-  const uint64_t slot = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
-  const uint32_t set = slot < n_slots ? a.st_set[slot] : kInactive;
-  (void)claim_by_key(counts, set, set != kInactive);
+  __shared__ GroupTable t;
+  group_table_init(t);
+  __syncthreads();
+  const uint64_t tile = (uint64_t)blockIdx.x * kGroupTile;
+#pragma unroll
+  for (int i = 0; i < kGroupPerThread; ++i) {
+    const uint64_t slot = tile + (uint64_t)i * kBlockThreads + threadIdx.x;
+    const uint32_t set = slot < n_slots ? a.st_set[slot] : kInactive;
+    const bool act = set != kInactive;
+    const uint32_t e = group_table_add(t, set, act);
+    (void)claim_by_key(counts, set, act && e == kNoEntry);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kGroupTable; i += kBlockThreads)
+    if (t.key[i] != kEmpty) atomicAdd(&counts[t.key[i]], (unsigned long long)t.cnt[i]);
 }
 
-// Exclusive prefix sum of counts[0, n) in place, by one workgroup, each
-// count rounded up to a multiple of `align` (64: every set's slots start a
-// wavefront, so none holds two sets); the total goes to ctr->compact.
+// first[i] = exclusive prefix sum of counts rounded up to multiples of
+// `align` (64: every set's slots start a wavefront, so none holds two sets),
+// counts cleared for the next regroup, the total in ctr->compact.  One
+// workgroup: each thread sums a contiguous range, a wavefront scan and an
+// LDS pass combine the ranges.
 constexpr int kScanThreads = 1024;
 
 __global__ __launch_bounds__(kScanThreads) void group_scan_kernel(unsigned long long* counts,
+                                                                  unsigned long long* first,
                                                                   uint64_t n, uint32_t align,
                                                                   Counters* ctr) {
-  __shared__ unsigned long long part[kScanThreads];
+  __shared__ unsigned long long wave_sum[kScanThreads / kWave];
   const uint64_t per = (n + kScanThreads - 1) / kScanThreads;
   const uint64_t b = (uint64_t)threadIdx.x * per;
   const uint64_t e = b + per < n ? b + per : n;
   const unsigned long long m = align - 1;
   unsigned long long sum = 0;
   for (uint64_t i = b; i < e; ++i) sum += (counts[i] + m) & ~m;
-  part[threadIdx.x] = sum;
+  // inclusive scan of the thread sums within the wavefront
+  const uint32_t lane = lane_id();
+  unsigned long long incl = sum;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const unsigned long long up = ((unsigned long long)(uint32_t)__shfl_up((int)(uint32_t)(incl >> 32), off) << 32) |
+                                  (uint32_t)__shfl_up((int)(uint32_t)incl, off);
+    if (lane >= (uint32_t)off) incl += up;
+  }
+  const int wave = threadIdx.x / kWave;
+  if (lane == kWave - 1) wave_sum[wave] = incl;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long run = 0;
-    for (int i = 0; i < kScanThreads; ++i) {
-      const unsigned long long v = part[i];
-      part[i] = run;
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+      const unsigned long long v = wave_sum[w];
+      wave_sum[w] = run;
       run += v;
     }
     ctr->compact = run;
   }
   __syncthreads();
-  unsigned long long run = part[threadIdx.x];
+  unsigned long long run = wave_sum[wave] + incl - sum;
   for (uint64_t i = b; i < e; ++i) {
     const unsigned long long v = (counts[i] + m) & ~m;
-    counts[i] = run;
+    first[i] = run;
+    counts[i] = 0;
     run += v;
   }
 }
 
-// Moves each active slot to the next position of its set (first[] from the
-// scan); dst's set array must already mark every slot inactive.
+// Moves each active slot of the tile to the next position of its set
+// (first[] from the scan): the tile's count per set reserves one range per
+// set with a global atomic, the lanes take positions in it from LDS.  dst's
+// set array must already mark every slot inactive.
 __global__ __launch_bounds__(kBlockThreads) void group_move_kernel(SliceArgs src, SliceArgs dst,
                                                                    uint64_t n_slots,
                                                                    unsigned long long* first) {
-  const uint64_t slot = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
-  const uint32_t set = slot < n_slots ? src.st_set[slot] : kInactive;
-  const bool act = set != kInactive;
-  const uint64_t pos = claim_by_key(first, set, act);
-  if (!act) return;
-  dst.st_set[pos] = set;
-  dst.st_idx[pos] = src.st_idx[slot];
-  dst.st_j[pos] = src.st_j[slot];
-  dst.st_phi[pos] = src.st_phi[slot];
-  dst.st_v[pos] = src.st_v[slot];
+  __shared__ GroupTable t;
+  group_table_init(t);
+  __syncthreads();
+  const uint64_t tile = (uint64_t)blockIdx.x * kGroupTile;
+  uint32_t set[kGroupPerThread], entry[kGroupPerThread];
+#pragma unroll
+  for (int i = 0; i < kGroupPerThread; ++i) {
+    const uint64_t slot = tile + (uint64_t)i * kBlockThreads + threadIdx.x;
+    set[i] = slot < n_slots ? src.st_set[slot] : kInactive;
+    entry[i] = group_table_add(t, set[i], set[i] != kInactive);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kGroupTable; i += kBlockThreads) {
+    if (t.key[i] != kEmpty) {
+      t.base[i] = atomicAdd(&first[t.key[i]], (unsigned long long)t.cnt[i]);
+      t.cnt[i] = 0;
+    }
+  }
+  __syncthreads();
+  const uint64_t lane_bit = 1ull << lane_id();
+#pragma unroll
+  for (int i = 0; i < kGroupPerThread; ++i) {
+    const uint64_t slot = tile + (uint64_t)i * kBlockThreads + threadIdx.x;
+    const bool act = set[i] != kInactive;
+    const bool in_table = act && entry[i] != kNoEntry;
+    // positions from the tile's reservation, one LDS atomic per entry
+    uint64_t pos = 0;
+    uint64_t pending = __ballot(in_table);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t le = (uint32_t)__builtin_amdgcn_readlane((int)entry[i], leader);
+      const uint64_t same = __ballot(in_table && entry[i] == le) & pending;
+      uint32_t off = 0;
+      if (lane_id() == (uint32_t)leader) off = atomicAdd(&t.cnt[le], (uint32_t)__popcll(same));
+      off = (uint32_t)__builtin_amdgcn_readlane((int)off, leader);
+      if (same & lane_bit) pos = t.base[le] + off + rank_in(same);
+      pending &= ~same;
+    }
+    // sets the table could not hold: one global atomic per wavefront
+    const uint64_t pos_g = claim_by_key(first, set[i], act && !in_table);
+    if (act && !in_table) pos = pos_g;
+    if (act) {
+      dst.st_set[pos] = set[i];
+      dst.st_idx[pos] = src.st_idx[slot];
+      dst.st_j[pos] = src.st_j[slot];
+      dst.st_phi[pos] = src.st_phi[slot];
+      dst.st_v[pos] = src.st_v[slot];
+    }
+  }
 }
 
 // After a move in set order (the sets' wavefront-aligned slots fill
 // [0, ctr->compact)), the free slots past them take the next undrawn replicas
 // in queue order.  The cursor stays a multiple of 64 (so does every draw of a
 // whole wavefront), so each new wavefront holds one work-queue chunk: one set.
+// (The cursor moves past them in copy_state_kernel, which runs next.)
 template <bool FP64>
 __global__ __launch_bounds__(kBlockThreads) void group_refill_kernel(SliceArgs a,
                                                                      uint64_t n_slots) {
@@ -1032,21 +1153,22 @@ __global__ __launch_bounds__(kBlockThreads) void group_refill_kernel(SliceArgs a
   store_slot(a, pos, s);
 }
 
-// The cursor past the replicas the refill took (never past `total`).
-__global__ void group_advance_kernel(Counters* ctr, uint64_t n_slots,
-                                     unsigned long long total) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  const unsigned long long active = ctr->compact;
-  const unsigned long long cursor = ctr->cursor;
-  if (cursor >= total) return;
-  const unsigned long long free = active < n_slots ? n_slots - active : 0ull;
-  ctr->cursor = cursor + (free < total - cursor ? free : total - cursor);
-}
-
-// Lane state of n_slots slots from src to dst.
+// Lane state of n_slots slots from src to dst; with `advance`, also the
+// cursor past the replicas the refill took (never past `total`).
 __global__ __launch_bounds__(kBlockThreads) void copy_state_kernel(SliceArgs src, SliceArgs dst,
-                                                                   uint64_t n_slots) {
+                                                                   uint64_t n_slots,
+                                                                   int advance) {
   const uint64_t slot = (uint64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  if (advance && slot == 0) {
+    Counters* ctr = src.ctr;
+    const unsigned long long active = ctr->compact;
+    const unsigned long long cursor = ctr->cursor;
+    if (cursor < src.total) {
+      const unsigned long long free = active < n_slots ? n_slots - active : 0ull;
+      const unsigned long long left = src.total - cursor;
+      ctr->cursor = cursor + (free < left ? free : left);
+    }
+  }
   if (slot >= n_slots) return;
   dst.st_set[slot] = src.st_set[slot];
   dst.st_idx[slot] = src.st_idx[slot];
@@ -1268,20 +1390,16 @@ hipError_t launch_compact_move(const SliceArgs& src, const SliceArgs& dst, uint6
 }
 
 hipError_t launch_group_count(const SliceArgs& a, uint64_t n_slots, unsigned long long* counts,
-                              uint64_t n_sets, hipStream_t st) {
+                              unsigned long long* first, uint64_t n_sets, hipStream_t st) {
   if (n_sets == 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_u64_kernel, dim3((uint32_t)((n_sets + 255) / 256)), dim3(256), 0, st,
-                     counts, n_sets, 0ull);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   if (n_slots > 0) {
     hipLaunchKernelGGL(group_count_kernel,
-                       dim3((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads)),
+                       dim3((uint32_t)((n_slots + kGroupTile - 1) / kGroupTile)),
                        dim3(kBlockThreads), 0, st, a, n_slots, counts);
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, counts, n_sets,
+  hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, counts, first, n_sets,
                      (uint32_t)kWave, a.ctr);
   return hipGetLastError();
 }
@@ -1295,8 +1413,7 @@ hipError_t launch_group_move(const SliceArgs& src, const SliceArgs& dst, uint64_
     if (e != hipSuccess) return e;
   }
   if (n_slots == 0) return hipSuccess;
-  hipLaunchKernelGGL(group_move_kernel,
-                     dim3((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads)),
+  hipLaunchKernelGGL(group_move_kernel, dim3((uint32_t)((n_slots + kGroupTile - 1) / kGroupTile)),
                      dim3(kBlockThreads), 0, st, src, dst, n_slots, first);
   return hipGetLastError();
 }
@@ -1310,18 +1427,15 @@ hipError_t launch_group_refill(bool fp64, const SliceArgs& a, uint64_t n_slots,
   } else {
     hipLaunchKernelGGL(group_refill_kernel<false>, g, dim3(kBlockThreads), 0, st, a, n_slots);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(group_advance_kernel, dim3(1), dim3(64), 0, st, a.ctr, n_slots, a.total);
   return hipGetLastError();
 }
 
 hipError_t launch_copy_state(const SliceArgs& src, const SliceArgs& dst, uint64_t n_slots,
-                             hipStream_t st) {
+                             bool advance_cursor, hipStream_t st) {
   if (n_slots == 0) return hipSuccess;
   hipLaunchKernelGGL(copy_state_kernel,
                      dim3((uint32_t)((n_slots + kBlockThreads - 1) / kBlockThreads)),
-                     dim3(kBlockThreads), 0, st, src, dst, n_slots);
+                     dim3(kBlockThreads), 0, st, src, dst, n_slots, advance_cursor ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -25,21 +25,23 @@ hipError_t launch_init(bool fp64, const SliceArgs& a, uint64_t n_slots,
 hipError_t launch_compact_count(const SliceArgs& a, uint64_t n_slots, hipStream_t st);
 hipError_t launch_compact_move(const SliceArgs& src, const SliceArgs& dst, uint64_t n_slots,
                                uint64_t n_dst_slots, hipStream_t st);
-// Grouping by set (multi-set plans and the server): counts[0, n_sets) gets
-// the first position of each set's active slots in set order, each set
-// starting a wavefront, and ctr->compact the end of the last set's
-// wavefronts; the move then writes them there in dst (n_dst_slots slots, all
-// others marked free).  n_dst_slots must be at least ctr->compact.
+// Grouping by set (multi-set plans and the server).  launch_group_count:
+// first[0, n_sets) gets the first position of each set's active slots in set
+// order, each set starting a wavefront, and ctr->compact the end of the last
+// set's wavefronts; counts[0, n_sets) must be zero and is left zero.  The
+// move then writes the slots there in dst (n_dst_slots slots, all others
+// marked free); n_dst_slots must be at least ctr->compact.
 hipError_t launch_group_count(const SliceArgs& a, uint64_t n_slots, unsigned long long* counts,
-                              uint64_t n_sets, hipStream_t st);
+                              unsigned long long* first, uint64_t n_sets, hipStream_t st);
 hipError_t launch_group_move(const SliceArgs& src, const SliceArgs& dst, uint64_t n_slots,
                              uint64_t n_dst_slots, unsigned long long* first, hipStream_t st);
-// Refill of the free slots past ctr->compact with the next undrawn replicas
-// (and the cursor past them), after a move in set order.
+// Refill of the free slots past ctr->compact with the next undrawn replicas,
+// after a move in set order; the copy of the state back then also moves the
+// cursor past them (advance_cursor).
 hipError_t launch_group_refill(bool fp64, const SliceArgs& a, uint64_t n_slots,
                                hipStream_t st);
 hipError_t launch_copy_state(const SliceArgs& src, const SliceArgs& dst, uint64_t n_slots,
-                             hipStream_t st);
+                             bool advance_cursor, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n,
                            unsigned long long value, hipStream_t st);
 hipError_t launch_rng_words(uint64_t seed, uint64_t replica0, uint64_t n_rep,

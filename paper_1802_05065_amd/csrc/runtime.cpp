@@ -222,8 +222,8 @@ fpt_status Plan::layout() {
     off = align256(off + 8 * slots);
     off_alt_set = off;
     off = align256(off + 4 * slots);
-    off_group = off;
-    if (multi) off = align256(off + sizeof(unsigned long long) * sets.size());
+    off_group = off;  // per-set counts, then per-set first positions
+    if (multi) off = align256(off + 2 * sizeof(unsigned long long) * sets.size());
   }
   ws_bytes = off;
   return FPT_OK;
@@ -294,6 +294,12 @@ fpt_status Plan::reset_run(const SliceArgs& a, uint64_t n_lanes_, int R, bool re
   FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(a.mom),
                           sizeof(MomDev) / 8 * sets.size(), 0ull, st));
   FPT_HIP(launch_fill_u64(a.hist, hist_bins, 0ull, st));
+  if (multi && has_alt) {
+    // the regroup's per-set counts (the workspace starts where a.sets points)
+    char* ws = const_cast<char*>(reinterpret_cast<const char*>(a.sets)) - off_sets;
+    FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws + off_group), sets.size(),
+                            0ull, st));
+  }
   const uint64_t n_slots = n_lanes_ * (uint64_t)R;
   const uint64_t n_assign = std::min<uint64_t>(n_slots, total_flat);
   FPT_HIP(launch_init(precision == FPT_FP64, a, n_slots, n_assign, st));
@@ -366,10 +372,11 @@ fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes
   const uint64_t done = (uint64_t)h_ctr->done;
   const uint64_t active_bound = total_flat - std::min<uint64_t>(done, total_flat);
   if (active_bound * 100 > slots * kCompactTriggerPercent) return FPT_OK;
-  auto* first = reinterpret_cast<unsigned long long*>(ws + off_group);
+  auto* counts = reinterpret_cast<unsigned long long*>(ws + off_group);
+  auto* first = counts + sets.size();
   FPT_HIP(launch_fill_u64(&a.ctr->compact, 1, 0ull, st));
   if (multi) {
-    FPT_HIP(launch_group_count(a, slots, first, sets.size(), st));
+    FPT_HIP(launch_group_count(a, slots, counts, first, sets.size(), st));
   } else {
     FPT_HIP(launch_compact_count(a, slots, st));
   }
@@ -408,15 +415,18 @@ fpt_status Plan::maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes
 // comes back, so wavefronts hold one set again (inside a launch only
 // wavefronts free in every lane draw new replicas).  Six small kernels, no
 // host synchronization, so a captured group of launches includes them.
+// (The per-set counts they use are zero at the start of a run and after
+// every count.)
 fpt_status Plan::enqueue_regroup(char* ws, const SliceArgs& a, int buf, uint64_t lanes, int R,
                                  hipStream_t st) {
   const uint64_t slots = lanes * (uint64_t)R;
   const SliceArgs other = slice_args(ws, reinterpret_cast<uint64_t*>(a.hist), lanes, 1 - buf);
-  auto* first = reinterpret_cast<unsigned long long*>(ws + off_group);
-  FPT_HIP(launch_group_count(a, slots, first, sets.size(), st));
+  auto* counts = reinterpret_cast<unsigned long long*>(ws + off_group);
+  auto* first = counts + sets.size();
+  FPT_HIP(launch_group_count(a, slots, counts, first, sets.size(), st));
   FPT_HIP(launch_group_move(a, other, slots, slots, first, st));
   FPT_HIP(launch_group_refill(precision == FPT_FP64, other, slots, st));
-  FPT_HIP(launch_copy_state(other, a, slots, st));
+  FPT_HIP(launch_copy_state(other, a, slots, true, st));
   return FPT_OK;
 }
 

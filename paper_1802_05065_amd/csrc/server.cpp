@@ -217,7 +217,7 @@ fpt_status Server::setup() {
   off_alt[2] = take(8 * n_slots);
   off_alt[3] = take(8 * n_slots);
   off_alt[4] = take(4 * n_slots);
-  off_group = take(sizeof(unsigned long long) * kMaxSets);
+  off_group = take(2 * sizeof(unsigned long long) * kMaxSets);  // counts, first positions
   cur_lanes = n_lanes;
   if (off + sizeof(Chunk) * kMinRingChunks + 8 * FPT_MAX_BINS > pool_bytes)
     return fail(FPT_E_NOMEM, "pool of %zu bytes cannot hold the lane state (%llu bytes) "
@@ -241,6 +241,8 @@ fpt_status Server::setup() {
                           0ull, stream));
   FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(a.mom),
                           sizeof(MomDev) / 8 * kMaxSets, 0ull, stream));
+  FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(pool + off_group), kMaxSets,
+                          0ull, stream));
   FPT_HIP(launch_init(precision == FPT_FP64, a, n_slots, 0, stream));
   FPT_HIP(hipStreamSynchronize(stream));
   return FPT_OK;
@@ -340,11 +342,12 @@ fpt_status Server::step() {
     // queue order (lanes of a wavefront share a set again)
     const uint64_t slots = a.n_lanes * (uint64_t)tuning.replicas_per_lane;
     const SliceArgs other = args_for(1 - buf_seen, a.n_lanes);
-    auto* first = reinterpret_cast<unsigned long long*>(pool + off_group);
-    FPT_HIP(launch_group_count(a, slots, first, kMaxSets, stream));
+    auto* counts = reinterpret_cast<unsigned long long*>(pool + off_group);
+    auto* first = counts + kMaxSets;
+    FPT_HIP(launch_group_count(a, slots, counts, first, kMaxSets, stream));
     FPT_HIP(launch_group_move(a, other, slots, slots, first, stream));
     FPT_HIP(launch_group_refill(precision == FPT_FP64, other, slots, stream));
-    FPT_HIP(launch_copy_state(other, a, slots, stream));
+    FPT_HIP(launch_copy_state(other, a, slots, true, stream));
     ++stats.n_regroups;
   }
   FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
@@ -376,8 +379,9 @@ fpt_status Server::maybe_compact_locked() {
   const uint64_t active_bound = h_ctr->cursor - std::min<uint64_t>(h_ctr->cursor, h_ctr->done);
   if (active_bound * 10 > slots * 8) return FPT_OK;
   const SliceArgs a = args();
-  auto* first = reinterpret_cast<unsigned long long*>(pool + off_group);
-  FPT_HIP(launch_group_count(a, slots, first, kMaxSets, stream));
+  auto* counts = reinterpret_cast<unsigned long long*>(pool + off_group);
+  auto* first = counts + kMaxSets;
+  FPT_HIP(launch_group_count(a, slots, counts, first, kMaxSets, stream));
   FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
   FPT_HIP(hipStreamSynchronize(stream));
   const uint64_t active = h_ctr->compact;
