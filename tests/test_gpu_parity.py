@@ -387,6 +387,29 @@ def test_uneven_full_size_fp64_sampled():
     assert np.mean(gpu[idx] == ref) >= 0.99
 
 
+def test_batched_full_size_sets_alone():
+    # the 256-set batched workload at its full size (5.4e6 replicas; ramps 10x
+    # faster so the run takes seconds), autotuned as in the benchmark: the
+    # multi-set kernel, the regroups after every launch and the longest-first
+    # queue leave every replica the result it has in a plan of its own
+    sets = workloads.batched_sets(n_sets=256, seed=4, ramp_scale=10.0)
+    res = api.simulate(sets, "fp32c", None)
+    st = res.stats
+    print(f"batched full size: {st['n_launches']} launches, {st['n_regroups']} regroups, "
+          f"{st['extra_passes']} extra passes, tuning {st['tuning']}")
+    assert st["n_regroups"] >= 1
+    assert st["extra_passes"] == 0  # set regions start wavefronts: no mixed wavefront
+    for i, s in enumerate(sets):
+        m = res.moments[i]
+        assert m["n_escaped"] + m["n_censored"] == s["n_replicas"], i
+    work = [s["n_replicas"] * s["max_steps"] for s in sets]
+    for i in np.argsort(work)[:4]:
+        alone = api.simulate(sets[int(i)], "fp32c",
+                             dict(replicas_per_lane=1, waves_per_simd=2, steps_per_launch=8192))
+        assert np.array_equal(_steps(res, int(i)), _steps(alone)), int(i)
+        assert res.counts[int(i)].tolist() == alone.counts[0].tolist()
+
+
 def test_switching_fp64_subset_matches_oracle():
     # the benchmark workload's first replicas in the literal FP64 path
     p = workloads.switching_ramp(n_replicas=256, seed=2)
