@@ -13,6 +13,14 @@
 // Without `refill` each slot keeps the replica assigned at the start
 // (one realization per thread, Algorithm 1's launch).
 //
+// Several parameter sets: a wavefront integrates a block for the lanes of
+// one set at a time, with that set's constants and Philox key in scalar
+// registers.  Multi-set refill runs keep wavefronts to one set: between
+// launches the active slots are sorted by set (each set starting a
+// wavefront) and the free slots refilled in queue order, and inside a launch
+// only a wavefront free in every lane draws (64 replicas, one chunk of one
+// set); such a wavefront runs its blocks with the constants fixed.
+//
 // With MT set the words of a block come from the replica's own MT19937
 // (Algorithm 2), whose state stays in device memory (mt19937.hpp); a slot
 // seeds it when it takes a new replica.
