@@ -136,12 +136,16 @@ typedef struct fpt_tuning {
                                 whose active replicas fill at most 80% of the
                                 slots moves them to a dense prefix and narrows
                                 later launches; results do not change */
-  int32_t no_regroup;        /* 1: never regroup.  Otherwise, when the lanes of a
-                                multi-set refill plan's wavefronts have come to
-                                hold replicas of several sets (a block then takes
-                                one pass per set), the active replicas' state is
-                                moved into set order between launches; results
-                                do not change */
+  int32_t no_regroup;        /* Multi-set refill plans (and the server) keep each
+                                wavefront to one set: after every launch while
+                                undrawn replicas remain, the active replicas'
+                                state moves into set order (each set starting a
+                                wavefront) and the free slots past them take the
+                                next replicas; inside a launch only wavefronts
+                                free in every lane draw.  1: no regrouping, and
+                                every free slot draws at once (wavefronts then
+                                mix sets and a block takes one pass per set).
+                                Results do not change */
   int32_t reserved;
 } fpt_tuning;
 
@@ -216,8 +220,9 @@ void fpt_plan_destroy(fpt_plan_t plan);
  * already running.  While every admitted replica has been drawn, the loop
  * packs the running ones into fewer lanes as they finish (tail compaction),
  * which speeds up each remaining replica; an admission restores the full
- * width.  Errors: FPT_E_NOMEM if the pool cannot hold the fixed
- * lane state. */
+ * width.  While replicas wait, each launch is followed by a regroup into set
+ * order as for plans (tuning->no_regroup).  Errors: FPT_E_NOMEM if the pool
+ * cannot hold the fixed lane state. */
 fpt_status fpt_server_create(void* device_pool, size_t pool_bytes,
                              int32_t precision, int32_t model,
                              const fpt_tuning* tuning, void* stream,
