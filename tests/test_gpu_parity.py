@@ -300,7 +300,8 @@ def test_batched_sets_equal_each_set_alone():
         assert np.mean(_steps(batch, i)[:8] == ref) >= 0.99
 
 
-def test_serving_alone_equals_mix():
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_serving_alone_equals_mix(prec):
     import time
 
     import torch
@@ -311,7 +312,7 @@ def test_serving_alone_equals_mix():
     pool = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     base = pool.data_ptr() + ((-pool.data_ptr()) % 256)
     stream = torch.cuda.current_stream()
-    srv = _lib.fpt_server_create(base, (256 << 20) - 256, "fp32c", 0,
+    srv = _lib.fpt_server_create(base, (256 << 20) - 256, prec, 0,
                                  dict(waves_per_simd=2, steps_per_launch=1024),
                                  stream.cuda_stream)
     try:
@@ -343,7 +344,7 @@ def test_serving_alone_equals_mix():
     finally:
         _lib.fpt_server_destroy(srv)
     for i, j in enumerate(jobs):
-        alone = api.simulate(j, "fp32c", FIXED, record_steps=False)
+        alone = api.simulate(j, prec, FIXED, record_steps=False)
         counts, mom, lat = results[i]
         assert counts.tolist() == alone.counts[0].tolist(), i
         for k in INT_MOMENTS:
