@@ -72,7 +72,8 @@ struct alignas(16) Counters {
   unsigned long long lane_steps;  // lane-steps issued, idle lanes included
   unsigned long long compact;     // active slots found by a compaction pass
   unsigned long long extra_passes;  // multi-set blocks: passes beyond one per slot
-  unsigned long long pad[3];
+  unsigned long long overflow;    // slots a move could not place (never expected)
+  unsigned long long pad[2];
 };
 
 // Arguments of one integrator launch.

@@ -1088,6 +1088,7 @@ __global__ __launch_bounds__(kScanThreads) void group_scan_kernel(unsigned long 
 // set array must already mark every slot inactive.
 __global__ __launch_bounds__(kBlockThreads) void group_move_kernel(SliceArgs src, SliceArgs dst,
                                                                    uint64_t n_slots,
+                                                                   uint64_t n_dst_slots,
                                                                    unsigned long long* first) {
   __shared__ GroupTable t;
   group_table_init(t);
@@ -1130,7 +1131,10 @@ __global__ __launch_bounds__(kBlockThreads) void group_move_kernel(SliceArgs src
     // sets the table could not hold: one global atomic per wavefront
     const uint64_t pos_g = claim_by_key(first, set[i], act && !in_table);
     if (act && !in_table) pos = pos_g;
-    if (act) {
+    // positions stay below the aligned total, which fits the slots while
+    // every wavefront holds one set; anything else is counted, not written
+    if (act && pos >= n_dst_slots) atomicAdd(&src.ctr->overflow, 1ull);
+    if (act && pos < n_dst_slots) {
       dst.st_set[pos] = set[i];
       dst.st_idx[pos] = src.st_idx[slot];
       dst.st_j[pos] = src.st_j[slot];
@@ -1422,7 +1426,7 @@ hipError_t launch_group_move(const SliceArgs& src, const SliceArgs& dst, uint64_
   }
   if (n_slots == 0) return hipSuccess;
   hipLaunchKernelGGL(group_move_kernel, dim3((uint32_t)((n_slots + kGroupTile - 1) / kGroupTile)),
-                     dim3(kBlockThreads), 0, st, src, dst, n_slots, first);
+                     dim3(kBlockThreads), 0, st, src, dst, n_slots, n_dst_slots, first);
   return hipGetLastError();
 }
 

@@ -537,6 +537,9 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       launches += group;
       if (graph_regroup) stats.n_regroups += group;
       blocks_issued += (uint64_t)group * (uint64_t)a.blocks;
+      if (h_ctr->overflow)
+        return fail(FPT_E_DEVICE, "regroup could not place %llu slots",
+                    (unsigned long long)h_ctr->overflow);
       finished = h_ctr->done >= total_replicas;
       if (!finished && blocks_issued > bound_blocks)
         return fail(FPT_E_DEVICE, "run did not finish within %llu steps per slot",
@@ -583,6 +586,9 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
       }
       marks.clear();
       ev_used = 0;
+      if (h_ctr->overflow)
+        return fail(FPT_E_DEVICE, "regroup could not place %llu slots",
+                    (unsigned long long)h_ctr->overflow);
       finished = h_ctr->done >= total_replicas;
       if (!finished && blocks_issued > bound_blocks)
         return fail(FPT_E_DEVICE, "run did not finish within %llu steps per slot",

@@ -356,6 +356,7 @@ fpt_status Server::step() {
   FPT_HIP(hipStreamSynchronize(stream));
   std::lock_guard<std::mutex> lk(mu);
   ++stats.n_launches;
+  if (h_ctr->overflow) return fail(FPT_E_DEVICE, "regroup could not place slots");
   cursor_seen = h_ctr->cursor;
   for (int32_t i = 0; i < kMaxSets; ++i) {
     Job* j = slot_job[(size_t)i];
