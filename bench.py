@@ -355,6 +355,31 @@ MT_BYTES_PER_REPLICA_STEP = 48 / 4.0
 PEAK_HBM = 8.0e12
 
 
+def streaming_rate(reads: int) -> float:
+    """Bytes/s of a plain device streaming kernel over 1 GiB operands with
+    `reads` reads per write (torch copy for 1, elementwise add for 2): the
+    rate an HBM-bound kernel with that read/write mix can attain here."""
+    import torch
+
+    n = 1 << 28
+    a = torch.rand(n, device="cuda")
+    b = torch.rand(n, device="cuda")
+    c = torch.empty_like(a)
+    fn = (lambda: c.copy_(a)) if reads == 1 else (lambda: torch.add(a, b, out=c))
+    for _ in range(3):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    rate = (reads + 1) * 4 * n / (e0.elapsed_time(e1) / 20 * 1e-3)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return rate
+
+
 def mt_mode(args):
     """The switching workload drawn from Algorithm 2's generator (one MT19937
     per replica) against the same workload on Philox4x32-10, both FP32C."""
@@ -387,9 +412,13 @@ def mt_mode(args):
                "avg_launch_ms": st["kernel_ms"] / max(st["n_launches"], 1)}
         if code:
             bw = st["replica_steps"] * MT_BYTES_PER_REPLICA_STEP / kernel_s
+            # the generator state moves two 16 B reads per 16 B write
+            attain = streaming_rate(2)
             leg["roofline"] = {"bound": "hbm", "achieved": bw / 1e9, "peak": PEAK_HBM / 1e9,
                                "unit": "GB/s", "frac": bw / PEAK_HBM,
-                               "bytes_per_replica_step": MT_BYTES_PER_REPLICA_STEP}
+                               "bytes_per_replica_step": MT_BYTES_PER_REPLICA_STEP,
+                               "streaming_2r1w_GBps": attain / 1e9,
+                               "frac_of_streaming": bw / attain}
         out[rng] = leg
         samples[rng] = r.steps[0].cpu().numpy()
         print(f"[bench] {rng}: {leg['replica_steps_per_s']:.4e} replica-steps/s",
