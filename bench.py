@@ -310,6 +310,21 @@ def uneven_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def batched_roofline(st):
+    """The headline's roofline terms for a multi-set run: algorithmic lane-ops
+    per replica-step over the kernel time (with a graph, the captured groups,
+    regroups included)."""
+    kernel_s = st["kernel_ms"] * 1e-3
+    if kernel_s <= 0:
+        return None
+    rate = st["replica_steps"] / kernel_s
+    mix = mix_attainable()
+    return {"bound": "alu", "achieved": rate * OPS_FP32C / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "TOP/s", "frac": rate * OPS_FP32C / PEAK_LANE_OPS,
+            "ops_per_replica_step": OPS_FP32C,
+            "frac_of_mix_attainable": rate / mix if mix else None}
+
+
 def batched_mode(args):
     """The 256-set workload in one plan: persistent refill over all sets,
     launches replayed through a captured hipGraph."""
@@ -338,6 +353,7 @@ def batched_mode(args):
             "regroups": st["n_regroups"], "compactions": st["n_compactions"],
             # passes beyond one per wavefront block for lanes of other sets
             "extra_pass_fraction": st["extra_passes"] / max(st["lane_steps"] / 256, 1),
+            "roofline": batched_roofline(st),
             "tuning": st["tuning"],
             "censored": int(sum(m["n_censored"] for m in r.moments))}
         if graph:
