@@ -125,6 +125,8 @@ def parse():
                     help="arrival window of the serving leg (0: skip)")
     ap.add_argument("--serve-drain", type=float, default=60.0,
                     help="longest wait for admitted jobs after the window")
+    ap.add_argument("--serve-steps", type=int, default=0,
+                    help="steps per launch of the serving loop (0: the server's default)")
     ap.add_argument("--serve-rho", type=float, default=0.7,
                     help="offered load of the rate-scaled trace, as a fraction of the "
                          "measured FP32C throughput")
@@ -193,7 +195,8 @@ def cpu_baseline(n_rep: int, procs: int):
                       f"{wall:.1f} s wall; host CPU: {cpu}"}
 
 
-def serving_leg(capacity: float, window_s: float, drain_s: float, rho: float):
+def serving_leg(capacity: float, window_s: float, drain_s: float, rho: float,
+                steps_per_launch: int = 0):
     """Continuous batching: the serving trace (Poisson arrivals at 50 jobs/s,
     ramp jobs with 2^10..2^18 replicas) offered at `rho` of the measured
     capacity by stretching its arrival times; jobs arriving in `window_s` are
@@ -215,7 +218,8 @@ def serving_leg(capacity: float, window_s: float, drain_s: float, rho: float):
     pool = torch.empty(pool_bytes + 256, dtype=torch.uint8, device="cuda")
     base = pool.data_ptr() + (-pool.data_ptr()) % 256
     stream = torch.cuda.Stream()
-    srv = _lib.fpt_server_create(base, pool_bytes, "fp32c", 0, None, stream.cuda_stream)
+    tun = dict(steps_per_launch=steps_per_launch) if steps_per_launch else None
+    srv = _lib.fpt_server_create(base, pool_bytes, "fp32c", 0, tun, stream.cuda_stream)
     pending, lat = {}, []
     i = 0
     t0 = time.perf_counter()
@@ -617,7 +621,8 @@ def main():
 
     latency = None
     if args.serve_seconds > 0:
-        latency = serving_leg(value, args.serve_seconds, args.serve_drain, args.serve_rho)
+        latency = serving_leg(value, args.serve_seconds, args.serve_drain, args.serve_rho,
+                              args.serve_steps)
         print(f"[bench] serving: {latency['finished']} jobs, p50 {latency['p50_s']} s, "
               f"p99 {latency['p99_s']} s", file=sys.stderr, flush=True)
 
