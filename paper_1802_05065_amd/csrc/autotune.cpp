@@ -128,7 +128,7 @@ static fpt_status trial(Plan& p, char* ws, hipStream_t st, const fpt_tuning& t,
   a.blocks = 256;
   a.refill = refill ? 1 : 0;
   a.whole_waves = p.regroups(t) ? 1 : 0;
-  FPT_TRY(p.reset_run(a, lanes, R, refill, st));
+  FPT_TRY(p.reset_run(ws, a, lanes, R, refill, st));
   FPT_TRY(p.ensure_host_resources(3));
   const uint32_t groups = (uint32_t)(lanes / kBlockThreads);
   const bool fp64 = p.precision == FPT_FP64;

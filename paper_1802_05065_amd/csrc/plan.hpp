@@ -75,7 +75,7 @@ struct Plan {
   uint64_t launch_bound(uint64_t n_slots, int blocks) const;
   fpt_status ensure_host_resources(size_t n_events);
   fpt_status upload_sets(char* ws, const std::vector<SetDev>& table, hipStream_t st);
-  fpt_status reset_run(const SliceArgs& a, uint64_t n_lanes, int R, bool refill,
+  fpt_status reset_run(char* ws, const SliceArgs& a, uint64_t n_lanes, int R, bool refill,
                        hipStream_t st);
   fpt_status resolve_tuning(char* ws, hipStream_t st);
   fpt_status simulate(void* workspace, int64_t* const* out_steps, uint64_t* out_hist,

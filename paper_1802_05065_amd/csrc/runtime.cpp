@@ -287,19 +287,16 @@ fpt_status Plan::ensure_host_resources(size_t n_events) {
 
 // Reset counters, results and lane state, then bind every slot's first
 // replica.  `sets_dev` already holds the set table.
-fpt_status Plan::reset_run(const SliceArgs& a, uint64_t n_lanes_, int R, bool refill,
+fpt_status Plan::reset_run(char* ws, const SliceArgs& a, uint64_t n_lanes_, int R, bool refill,
                            hipStream_t st) {
   FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(a.ctr),
                           sizeof(Counters) / 8, 0ull, st));
   FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(a.mom),
                           sizeof(MomDev) / 8 * sets.size(), 0ull, st));
   FPT_HIP(launch_fill_u64(a.hist, hist_bins, 0ull, st));
-  if (multi && has_alt) {
-    // the regroup's per-set counts (the workspace starts where a.sets points)
-    char* ws = const_cast<char*>(reinterpret_cast<const char*>(a.sets)) - off_sets;
+  if (multi && has_alt)  // the regroup's per-set counts
     FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws + off_group), sets.size(),
                             0ull, st));
-  }
   const uint64_t n_slots = n_lanes_ * (uint64_t)R;
   const uint64_t n_assign = std::min<uint64_t>(n_slots, total_flat);
   FPT_HIP(launch_init(precision == FPT_FP64, a, n_slots, n_assign, st));
@@ -463,7 +460,7 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
   a.blocks = blocks;
   a.refill = refill ? 1 : 0;
   a.whole_waves = regroup ? 1 : 0;
-  FPT_TRY(reset_run(a, n_lanes, R, refill, st));
+  FPT_TRY(reset_run(ws, a, n_lanes, R, refill, st));
 
   uint64_t lanes = n_lanes;  // narrows at each tail compaction
   int buf = 0;
