@@ -207,9 +207,15 @@ def test_tail_compaction_keeps_results(prec):
                                        steps_per_launch=2048, no_compaction=1))
     b1 = api.simulate(sets, prec, dict(replicas_per_lane=1, waves_per_simd=2,
                                        steps_per_launch=2048))
-    for i in range(len(sets)):
-        assert np.array_equal(_steps(b0, i), _steps(b1, i)), i
-        assert b0.counts[i].tolist() == b1.counts[i].tolist()
+    # without regrouping wavefronts mix sets; compaction still moves the
+    # active state in (wavefront-aligned) set order
+    b2 = api.simulate(sets, prec, dict(replicas_per_lane=1, waves_per_simd=2,
+                                       steps_per_launch=2048, no_regroup=1))
+    assert b2.stats["n_regroups"] == 0
+    for b in (b1, b2):
+        for i in range(len(sets)):
+            assert np.array_equal(_steps(b0, i), _steps(b, i)), i
+            assert b0.counts[i].tolist() == b.counts[i].tolist()
 
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
