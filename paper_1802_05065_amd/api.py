@@ -88,6 +88,58 @@ class Plan:
             pass
 
 
+class Server:
+    """An fpt_server_t (continuous batching) with its torch-allocated device
+    pool and its own stream: ``submit`` queues a job (a dict with the fields
+    of ``fpt_params``) and returns its id, ``poll`` returns None while it runs,
+    else (counts, moments, latency_s)."""
+
+    def __init__(self, precision="fp32c", model: int = 0, tuning: Optional[Dict] = None,
+                 pool_bytes: int = 1 << 30, device=None):
+        torch = _torch()
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self._pool_raw, self.pool_ptr = _aligned_buffer(torch, pool_bytes, self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.n_bins: Dict[int, int] = {}
+        self.handle = _lib.fpt_server_create(self.pool_ptr, pool_bytes, precision, model,
+                                             tuning, self.stream.cuda_stream)
+
+    def submit(self, params: Dict) -> int:
+        job = _lib.fpt_submit(self.handle, params)
+        self.n_bins[job] = int(params["n_bins"])
+        return job
+
+    def poll(self, job: int):
+        return _lib.fpt_poll(self.handle, job, self.n_bins[job])
+
+    def wait(self, job: int, timeout_s: float = 600.0, interval_s: float = 0.005):
+        """Poll until the job is done; raises TimeoutError after timeout_s."""
+        import time
+
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(job)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"job {job} not done after {timeout_s} s")
+            time.sleep(interval_s)
+
+    def stats(self) -> Dict:
+        return _lib.fpt_server_stats_get(self.handle)
+
+    def close(self):
+        if self.handle:
+            _lib.fpt_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def simulate(sets, precision="fp64", tuning: Optional[Dict] = None,
              record_steps: bool = True) -> SimResult:
     """Run every replica of ``sets`` (a dict or a list of dicts with the fields of

@@ -358,6 +358,26 @@ def test_serving_alone_equals_mix(prec):
         assert lat > 0
 
 
+def test_api_server_jobs_equal_plans():
+    # the Python wrapper of the serving entry points: jobs submitted together
+    # give each job's plan results
+    jobs = workloads.batched_sets(n_sets=3, seed=13, log2_min=8, log2_max=10, ramp_scale=300.0)
+    srv = api.Server("fp32c", tuning=dict(waves_per_simd=2, steps_per_launch=2048),
+                     pool_bytes=256 << 20)
+    try:
+        ids = [srv.submit(j) for j in jobs]
+        res = [srv.wait(i, timeout_s=90.0) for i in ids]
+        assert srv.stats()["finished"] == len(jobs)
+    finally:
+        srv.close()
+    for j, (counts, mom, lat) in zip(jobs, res):
+        alone = api.simulate(j, "fp32c", FIXED, record_steps=False)
+        assert counts.tolist() == alone.counts[0].tolist()
+        for k in INT_MOMENTS:
+            assert mom[k] == alone.moments[0][k], k
+        assert lat > 0
+
+
 # ---------------------------------------------------------------------------
 # full workload sizes, in the benchmark's launch configuration (autotuned),
 # sampled replicas against the oracle
