@@ -316,13 +316,16 @@ fpt_status Plan::upload_sets(char* ws, const std::vector<SetDev>& table,
 
 // Upper bound on launches: no replica needs more than jmax+1 blocks, and all
 // replicas together cannot need more than their summed blocks spread over the
-// slots, plus the longest single replica for the tail.
+// slots, plus the longest single replica for the tail.  A multi-set run
+// counts every work-queue chunk as 64 replicas: a wavefront that takes a
+// chunk may keep all its lanes until the chunk's last replica is done.
 uint64_t Plan::launch_bound(uint64_t n_slots, int blocks) const {
   uint64_t longest = 0;
   long double work = 0;
   for (const SetDev& s : sets) {
     longest = std::max<uint64_t>(longest, s.jmax + 1);
-    work += (long double)s.n_replicas * (long double)(s.jmax + 1);
+    const uint64_t n = multi ? round_up(s.n_replicas, (uint64_t)kChunk) : s.n_replicas;
+    work += (long double)n * (long double)(s.jmax + 1);
   }
   const long double per_launch = (long double)n_slots * (long double)blocks;
   const uint64_t spread = (uint64_t)(work / per_launch) + 1;

@@ -287,6 +287,23 @@ def test_edge_cases_match_oracle():
             assert (gpu == -1).all()
 
 
+def test_many_small_sets_finish_with_their_own_results():
+    # sets much smaller than a wavefront: each work-queue chunk (64 replicas
+    # with padding) holds a wavefront until its last replica is done, for
+    # several rounds of chunks; every replica still gets its own result
+    base = workloads.switching_ramp(n_replicas=5, seed=1)
+    sets = [dict(base, ramp=3e-3, max_steps=7_000, hist_k_max=6_700, n_bins=32, seed=500 + i)
+            for i in range(4096)]
+    res = api.simulate(sets, "fp32c", dict(replicas_per_lane=1, waves_per_simd=1,
+                                           steps_per_launch=1024))
+    for i in range(len(sets)):
+        m = res.moments[i]
+        assert m["n_escaped"] + m["n_censored"] == 5, i
+    for i in (0, 1, 2047, 4095):
+        alone = api.simulate(sets[i], "fp32c", FIXED)
+        assert np.array_equal(_steps(res, i), _steps(alone)), i
+
+
 def test_batched_sets_equal_each_set_alone():
     sets = workloads.batched_sets(n_sets=6, seed=4, log2_min=6, log2_max=9, ramp_scale=300.0)
     for prec in ("fp64", "fp32c"):
