@@ -156,6 +156,26 @@ def test_plain_escape_fp32c_statistics():
           f"mean |dk| {np.abs(same32 - s64).mean():.1f}")
 
 
+def test_overdamped_fp32c_statistics():
+    # the overdamped model (the uneven workload) in FP32C against FP64 with
+    # an independent seed: same escape-time law (exponential tail), and the
+    # mean first-passage time near the exact quadrature value 356.8 / dt
+    n = 2 ** 15
+    p32 = workloads.uneven_overdamped(n_replicas=n, seed=303)
+    p64 = workloads.uneven_overdamped(n_replicas=n, seed=404)
+    s32 = _steps(api.simulate(p32, "fp32c", FIXED))
+    s64 = _steps(api.simulate(p64, "fp64", FIXED))
+    assert (s32 > 0).all() and (s64 > 0).all()
+    ks = stats.ks_2samp(s32, s64)
+    se = math.sqrt(s32.var() / n + s64.var() / n)
+    print(f"overdamped KS p = {ks.pvalue:.3f}; mean fp32c {s32.mean():.0f} fp64 "
+          f"{s64.mean():.0f} (3 SE = {3 * se:.0f})")
+    assert ks.pvalue > 0.01
+    assert abs(s32.mean() - s64.mean()) < 3 * se
+    # Euler at dt 0.01 against the continuous process: within 5%
+    assert abs(s32.mean() * p32["dt"] / 356.8 - 1.0) < 0.05
+
+
 TUNINGS = [
     dict(replicas_per_lane=1, waves_per_simd=8, steps_per_launch=1024),
     dict(replicas_per_lane=2, waves_per_simd=2, steps_per_launch=4096),
