@@ -75,11 +75,14 @@ static bool tune_verbose() {
   return v && v[0] == '1';
 }
 
+// Entries are kept per build of the library (its kernels may change the best
+// shape), per device, precision, model, schedule and single / multi set.
 std::string tune_key(const std::string& arch, int precision, int model, int schedule,
                      bool multi) {
-  char buf[160];
-  std::snprintf(buf, sizeof(buf), "%s/p%d/m%d/s%d/%s", arch.c_str(), precision, model,
-                schedule, multi ? "multi" : "single");
+  static const char kBuild[] = __DATE__ " " __TIME__;
+  char buf[200];
+  std::snprintf(buf, sizeof(buf), "%s/%s/p%d/m%d/s%d/%s", kBuild, arch.c_str(), precision,
+                model, schedule, multi ? "multi" : "single");
   return buf;
 }
 
