@@ -206,6 +206,14 @@ fpt_status fpt_simulate(fpt_plan_t plan, void* workspace,
 fpt_status fpt_histogram(fpt_plan_t plan, int32_t set, uint64_t* host_counts,
                          fpt_moments* host_m);
 
+/* Every set at once, with one device-to-host copy of the histograms and one
+ * of the moments (plans of many sets):
+ *   host_counts : host uint64[sum of n_bins], sets in plan order, or NULL
+ *   host_m      : host fpt_moments[n_sets], or NULL
+ * Synchronizes the last fpt_simulate's stream.  Errors: FPT_E_STATE before
+ * a simulate. */
+fpt_status fpt_histogram_all(fpt_plan_t plan, uint64_t* host_counts, fpt_moments* host_m);
+
 /* Counters and timing of the last fpt_simulate (synchronizes). */
 fpt_status fpt_plan_stats(fpt_plan_t plan, fpt_run_stats* out);
 

@@ -139,6 +139,8 @@ SIGNATURES = [
     ("fpt_simulate", ctypes.c_int, [_VP, _VP, ctypes.POINTER(_VP), _VP, _VP]),
     ("fpt_histogram", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
                                      ctypes.POINTER(FptMoments)]),
+    ("fpt_histogram_all", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(FptMoments)]),
     ("fpt_plan_stats", ctypes.c_int, [_VP, ctypes.POINTER(FptRunStats)]),
     ("fpt_plan_destroy", None, [_VP]),
     ("fpt_server_create", ctypes.c_int, [_VP, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
@@ -250,6 +252,20 @@ def fpt_histogram(plan: int, set_index: int, n_bins: int):
                               counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                               ctypes.byref(m)))
     return counts, moments_dict(m)
+
+
+def fpt_histogram_all(plan: int, n_bins: Sequence[int]):
+    """Every set's counts (list of arrays, plan order) and moments."""
+    total = int(sum(n_bins))
+    counts = np.zeros(max(total, 1), dtype=np.uint64)
+    moms = (FptMoments * max(len(n_bins), 1))()
+    check(lib().fpt_histogram_all(plan, counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  moms))
+    out_c, off = [], 0
+    for n in n_bins:
+        out_c.append(counts[off:off + int(n)].copy())
+        off += int(n)
+    return out_c, [moments_dict(moms[i]) for i in range(len(n_bins))]
 
 
 def fpt_plan_stats(plan: int) -> Dict:

@@ -69,11 +69,8 @@ class Plan:
                 ptrs.append(0)
         hist = torch.empty(max(self.n_bins_total, 1), dtype=torch.int64, device=self.device)
         _lib.fpt_simulate(self.handle, self.ws_ptr, ptrs, hist.data_ptr(), stream.cuda_stream)
-        counts, moments = [], []
-        for i, s in enumerate(self.sets):
-            c, m = _lib.fpt_histogram(self.handle, i, int(s["n_bins"]))
-            counts.append(c)
-            moments.append(m)
+        counts, moments = _lib.fpt_histogram_all(self.handle,
+                                                 [int(s["n_bins"]) for s in self.sets])
         return SimResult(steps, hist, counts, moments, _lib.fpt_plan_stats(self.handle))
 
     def close(self):

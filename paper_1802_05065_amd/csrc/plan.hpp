@@ -81,6 +81,7 @@ struct Plan {
   fpt_status simulate(void* workspace, int64_t* const* out_steps, uint64_t* out_hist,
                       hipStream_t st);
   fpt_status histogram(int32_t set, uint64_t* host_counts, fpt_moments* host_m);
+  fpt_status histogram_all(uint64_t* host_counts, fpt_moments* host_m);
   fpt_status run_stats(fpt_run_stats* out);
 };
 

@@ -637,6 +637,21 @@ fpt_status Plan::histogram(int32_t set, uint64_t* host_counts, fpt_moments* host
   return FPT_OK;
 }
 
+fpt_status Plan::histogram_all(uint64_t* host_counts, fpt_moments* host_m) {
+  if (!ran) return fail(FPT_E_STATE, "fpt_histogram_all before a finished fpt_simulate");
+  FPT_HIP(hipStreamSynchronize(stream));
+  if (host_counts && hist_bins > 0)
+    FPT_HIP(hipMemcpy(host_counts, hist_dev, sizeof(uint64_t) * hist_bins,
+                      hipMemcpyDeviceToHost));
+  if (host_m && !sets.empty()) {
+    std::vector<MomDev> m(sets.size());
+    FPT_HIP(hipMemcpy(m.data(), ws_mom_ptr, sizeof(MomDev) * sets.size(),
+                      hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < sets.size(); ++i) fill_moments(m[i], sets[i].dt, &host_m[i]);
+  }
+  return FPT_OK;
+}
+
 void fill_moments(const MomDev& m, double dt, fpt_moments* out) {
   out->n_escaped = m.n_esc;
   out->n_censored = m.n_cens;
@@ -812,6 +827,11 @@ fpt_status fpt_histogram(fpt_plan_t plan, int32_t set, uint64_t* host_counts,
                          fpt_moments* host_m) {
   if (!plan) return fpt::fail(FPT_E_INVAL, "plan is NULL");
   return plan->impl->histogram(set, host_counts, host_m);
+}
+
+fpt_status fpt_histogram_all(fpt_plan_t plan, uint64_t* host_counts, fpt_moments* host_m) {
+  if (!plan) return fpt::fail(FPT_E_INVAL, "plan is NULL");
+  return plan->impl->histogram_all(host_counts, host_m);
 }
 
 fpt_status fpt_plan_stats(fpt_plan_t plan, fpt_run_stats* out) {

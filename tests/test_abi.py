@@ -111,6 +111,9 @@ def test_histogram_before_simulate_is_a_state_error(lib):
         with pytest.raises(_lib.FptError) as e:
             _lib.fpt_histogram(h, 0, 64)
         assert e.value.status == _lib.FPT_E_STATE
+        with pytest.raises(_lib.FptError) as e:
+            _lib.fpt_histogram_all(h, [64])
+        assert e.value.status == _lib.FPT_E_STATE
     finally:
         _lib.fpt_plan_destroy(h)
 
@@ -121,6 +124,7 @@ def test_null_arguments(lib):
     assert lib.fpt_plan(None, 1, 0, None, ctypes.byref(ctypes.c_void_p())) == _lib.FPT_E_INVAL
     assert lib.fpt_plan_workspace(None, None) == _lib.FPT_E_INVAL
     assert lib.fpt_simulate(None, None, None, None, None) == _lib.FPT_E_INVAL
+    assert lib.fpt_histogram_all(None, None, None) == _lib.FPT_E_INVAL
     assert lib.fpt_server_create(None, 0, 0, 0, None, None,
                                  ctypes.byref(ctypes.c_void_p())) == _lib.FPT_E_INVAL
     assert lib.fpt_submit(None, None, None) == _lib.FPT_E_INVAL

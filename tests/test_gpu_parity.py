@@ -13,7 +13,7 @@ import pytest
 from scipy import stats
 
 import oracle
-from paper_1802_05065_amd import api, workloads
+from paper_1802_05065_amd import _lib, api, workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -322,6 +322,21 @@ def test_many_small_sets_finish_with_their_own_results():
     for i in (0, 1, 2047, 4095):
         alone = api.simulate(sets[i], "fp32c", FIXED)
         assert np.array_equal(_steps(res, i), _steps(alone)), i
+
+
+def test_histogram_all_equals_per_set_readback():
+    sets = workloads.batched_sets(n_sets=7, seed=17, log2_min=6, log2_max=9, ramp_scale=300.0)
+    plan = api.Plan(sets, "fp32c", FIXED)
+    try:
+        res = plan.run(record_steps=False)  # reads back with fpt_histogram_all
+        for i, s in enumerate(sets):
+            c, m = _lib.fpt_histogram(plan.handle, i, int(s["n_bins"]))
+            assert c.tolist() == res.counts[i].tolist(), i
+            for k in INT_MOMENTS:
+                assert m[k] == res.moments[i][k], (i, k)
+            assert m["mean_t"] == res.moments[i]["mean_t"]
+    finally:
+        plan.close()
 
 
 def test_batched_sets_equal_each_set_alone():
