@@ -28,15 +28,17 @@ if ROOT not in sys.path:
 METRIC = "replica-steps/s FP32-comp vs FP64 at KS-pass accuracy; p50/p99 job latency"
 
 # Algorithmic VALU lane-operations per replica-step of the FP32C path: the
-# method's minimal instruction mix per 4-step block, one lane-op per
-# instruction (sin and generator operations included):
+# method's operations per 4-step block, one lane-op per instruction (sin and
+# generator operations included):
 #   Philox4x32-10: 10 rounds x (2 32x32->64 products + 2 three-input XORs) = 40
-#   4 uniforms (convert + scale)                                            =  8
+#   4 uniforms (radii: convert + scale; angles: one bit-field insert)       =  6
 #   Box-Muller: 2 x (log, sqrt, cos, sin) + 2 noise scalings                = 10
 #   bias: 1 FP64 fma + 1 convert per block + 3 FP32 increments              =  5
-#   4 steps x (sin, 4 Kahan, 3 velocity fma, threshold compare)             = 36
+#   4 steps x (sin, phase advance fma, 3 velocity fma) + 3 phases of the
+#     block + compensated fold of the block's advance (add, 2 subtractions) = 26
+#   threshold: largest of the 4 phases (2) and one compare                  =  3
 #   block counter (FP64 step count, 64-bit block index)                     =  2
-OPS_FP32C = (40 + 8 + 10 + 5 + 36 + 2) / 4.0
+OPS_FP32C = (40 + 6 + 10 + 5 + 26 + 3 + 2) / 4.0
 # MI355X FP32 vector peak 157.3 TFLOP/s = 78.6e12 FMA lane-operations/s
 # (256 CUs x 128 FP32 lanes per clock x 2.4 GHz)
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
@@ -56,9 +58,10 @@ FP32C_BLOCK_MIX = {
     "bitop3_b32_s": 20,    # Philox three-input XORs
     "sin_f32": 6, "cos_f32": 2, "log_f32": 2,
     "sqrt_f32_neg": 2,     # Box-Muller radius, negated operand (VOP3 form)
-    "fmac_f32_s": 13,      # Kahan increment, noise, force, damping
-    "add_f32": 8,          # Kahan sums, bias offsets, near-threshold compare
-    "sub_f32": 7,          # Kahan error terms
+    "fmac_f32_s": 16,      # phase advance, noise, force, damping
+    "add_f32": 10,         # phases of the block, fold, bias offsets; priced alike:
+                           # near-threshold compare and 2 register copies
+    "sub_f32": 2,          # error term of the fold
     "mul_f32": 2, "fmamk_f32": 2,
     "cvt_f32_u32": 2,      # uniforms of the radii
     "cvt_f32_f64": 1,      # the block's bias G_k to FP32

@@ -47,7 +47,10 @@ __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1,
 // The same with a wavefront-uniform key: each round key is formed on the
 // scalar unit just before its round (the opaque copy stops the compiler from
 // hoisting all 20 into scalar registers at once, which would cost the
-// integrator a resident wave).
+// integrator a resident wave).  Round 0's product of the replica index is
+// the same for every block, but forming it here keeps the two product
+// chains of each round independent, which the scheduler interleaves; passed
+// in precomputed, it offsets the chains and the loop ran 5% slower.
 __device__ __forceinline__ Words philox4x32_10_uniform_key(uint32_t c0, uint32_t c1,
                                                            uint32_t c2, uint32_t c3,
                                                            uint32_t k0, uint32_t k1) {
@@ -147,8 +150,9 @@ struct ParF64 {
 
 // FP32C constants, phase in revolutions (phi / 2 pi):
 //   underdamped  v_k = damp v + G_k + nkS sin(2 pi phr) + sig z_k,
-//                phr_k = phr + h_rev v            (Kahan-compensated)
-//   overdamped   phr_k = phr + G_k + nkS sin(2 pi phr) + sig z_k  (compensated)
+//                phr_k = phr + h_rev v
+//   overdamped   phr_k = phr + G_k + nkS sin(2 pi phr) + sig z_k
+// (the phase sums Kahan-compensated once per block of 4 steps)
 // with G_k = gA + gB k evaluated in FP64 from the exact step k, nkS = -kS,
 // and dG, dG2, dG3 the bias offsets of a block's steps 2, 3, 4 from its first.
 struct ParF32 {
@@ -201,61 +205,58 @@ __device__ __forceinline__ void step_f64_over(const ParF64& p, double kd,
   phi = phi + p.dt * drift + p.sigma * r;
 }
 
-// FP32C steps.  The phase is the compensated pair (phr, e) in revolutions
-// with true value phr + e (Kahan summation of the increments, the error term
-// kept with the sign that makes every update an accumulation).  `a` enters
-// as G_k rounded to FP32 and is consumed; `zs` is the noise factor
-// sig*radius' and `trig` the cos or sin of the pair's angle.  Each update is
-// a multiply-add into a value that dies with it, so the compiler can use the
-// two-operand v_fmac_f32, which issues at twice the rate of the
+// FP32C steps.  Between blocks the phase is the compensated pair (phr, e)
+// in revolutions, true value phr + e.  Inside a block of 4 steps a plain
+// FP32 running sum d starts at e and takes the steps' increments (at most
+// 4 of them, so its own rounding stays far below one increment's noise);
+// step q+1 sees the phase x_q = phr + d_q, rounded once, and the block's
+// end splits phr + d_4 into the new pair with the error term of the
+// rounded sum (Fast2Sum: |phr| >= |d| near any threshold).  `a` enters as
+// G_k rounded to FP32 and is consumed; `zs` is the noise factor
+// sig*radius' and `trig` the cos or sin of the pair's angle.  Each update
+// is a multiply-add into a value that dies with it, so the compiler can use
+// the two-operand v_fmac_f32, which issues at twice the rate of the
 // three-operand v_fma_f32 on gfx950.
 
-// Compensated phr += inc, given y = inc + e; returns y.  The new error term
-// is y - (phr_new - phr_old), so it can be recomputed exactly from y and the
-// two phases (kahan_error).
-__device__ __forceinline__ float kahan_add(float y, float& phr, float& e) {
-  const float t = phr + y;
-  e = y - (t - phr);
-  phr = t;
-  return y;
-}
-
-__device__ __forceinline__ float kahan_error(float y, float phr_new, float phr_old) {
-  return y - (phr_new - phr_old);
-}
-
-// Underdamped, explicit (Algorithm 1): phase from the old velocity.
-__device__ __forceinline__ float step_f32_under(const ParF32& p, float a, float zs,
-                                                float trig, float& phr, float& e,
-                                                float& v) {
-  const float s = __builtin_amdgcn_sinf(phr);
-  const float y = kahan_add(__builtin_fmaf(p.h_rev, v, e), phr, e);
+// Underdamped, explicit (Algorithm 1): the phase advance uses the old
+// velocity.
+__device__ __forceinline__ void step_f32_under(const ParF32& p, float a, float zs,
+                                               float trig, float x, float& d, float& v) {
+  const float s = __builtin_amdgcn_sinf(x);
+  d = __builtin_fmaf(p.h_rev, v, d);
   a = __builtin_fmaf(zs, trig, a);
   a = __builtin_fmaf(p.nkS, s, a);
   v = __builtin_fmaf(p.damp, v, a);
-  return y;
 }
 
 // Underdamped, semi-implicit: the velocity first, then the phase moves with
 // the new velocity.
-__device__ __forceinline__ float step_f32_under_si(const ParF32& p, float a, float zs,
-                                                   float trig, float& phr, float& e,
-                                                   float& v) {
-  const float s = __builtin_amdgcn_sinf(phr);
+__device__ __forceinline__ void step_f32_under_si(const ParF32& p, float a, float zs,
+                                                  float trig, float x, float& d,
+                                                  float& v) {
+  const float s = __builtin_amdgcn_sinf(x);
   a = __builtin_fmaf(zs, trig, a);
   a = __builtin_fmaf(p.nkS, s, a);
   v = __builtin_fmaf(p.damp, v, a);
-  return kahan_add(__builtin_fmaf(p.h_rev, v, e), phr, e);
+  d = __builtin_fmaf(p.h_rev, v, d);
 }
 
-// Overdamped: the increment G_k - kS sin(2 pi phr) + sig z_k is added to the
-// compensated phase.
-__device__ __forceinline__ float step_f32_over(const ParF32& p, float a, float zs,
-                                               float trig, float& phr, float& e) {
-  const float s = __builtin_amdgcn_sinf(phr);
+// Overdamped: the increment G_k - kS sin(2 pi x) + sig z_k joins the
+// running sum.
+__device__ __forceinline__ void step_f32_over(const ParF32& p, float a, float zs,
+                                              float trig, float x, float& d) {
+  const float s = __builtin_amdgcn_sinf(x);
   a = __builtin_fmaf(zs, trig, a);
   a = __builtin_fmaf(p.nkS, s, a);
-  return kahan_add(a + e, phr, e);
+  d = d + a;
+}
+
+// End of a block: phr + d becomes the pair (phr', e') with phr' = phr + d
+// rounded and e' = d - (phr' - phr), the part of d that phr' lost.
+__device__ __forceinline__ void fold_advance(float d, float& phr, float& e) {
+  const float t = phr + d;
+  e = d - (t - phr);
+  phr = t;
 }
 
 // Bias terms G_k of a block's 4 steps: the first from the exact step count

@@ -454,14 +454,16 @@ __device__ __forceinline__ void block_f64(const SliceArgs& a, uint64_t n_slots,
 }
 
 // FP32C: the 4 steps of a block for NR slots sharing the constants P (gA:
-// P.p.gA in a vector register).  Records the phase after each step and the
-// compensated increments, from which the threshold test runs afterwards.
+// P.p.gA in a vector register).  Records the phase after each step for the
+// threshold test that runs afterwards: ph_q[q] for q = 1..3 is the FP32
+// phase x_q the next step sees, ph_q[4] the leading word of the new pair,
+// whose error term is the slot's e (ph_q[0]: the block's start).
 template <int MODEL, int NR, bool MT>
 __device__ __forceinline__ void block_f32(const SliceArgs& a, uint64_t n_slots,
                                           uint64_t lane_g, uint64_t lane_bit, int r0,
                                           const uint64_t* amask, MtCarry* mc,
                                           Slot<false>* s, const SetPar<false>& P, double gA,
-                                          float (*ph_q)[5], float (*y_q)[4]) {
+                                          float (*ph_q)[5]) {
   const ParF32& p = P.p;
   // generator and normals of every slot first, then the 4 steps with the
   // slots interleaved (independent chains for the scheduler)
@@ -484,64 +486,69 @@ __device__ __forceinline__ void block_f32(const SliceArgs& a, uint64_t n_slots,
     zs[r][0] = p.sig * bm[r].radius[0];
     zs[r][1] = p.sig * bm[r].radius[1];
   }
+  // the running sums start at the error terms, which they consume
+  float d[NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) ph_q[r][0] = s[r].phi;
+  for (int r = 0; r < NR; ++r) d[r] = s[r].e;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       Slot<false>& sl = s[r];
       const float trig = (q & 1) ? bm[r].s[q >> 1] : bm[r].c[q >> 1];
+      // the phase after step q: the block's start plus the running sum
+      const float x = q == 0 ? sl.phi : sl.phi + d[r];
+      ph_q[r][q] = x;
       if constexpr (MODEL == kUnderExplicit) {
-        y_q[r][q] = step_f32_under(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e, sl.v);
+        step_f32_under(p, gk[r].g[q], zs[r][q >> 1], trig, x, d[r], sl.v);
       } else if constexpr (MODEL == kUnderSemiImplicit) {
-        y_q[r][q] = step_f32_under_si(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e, sl.v);
+        step_f32_under_si(p, gk[r].g[q], zs[r][q >> 1], trig, x, d[r], sl.v);
       } else {
-        y_q[r][q] = step_f32_over(p, gk[r].g[q], zs[r][q >> 1], trig, sl.phi, sl.e);
+        step_f32_over(p, gk[r].g[q], zs[r][q >> 1], trig, x, d[r]);
       }
-      ph_q[r][q + 1] = sl.phi;
     }
   }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    fold_advance(d[r], s[r].phi, s[r].e);
+    ph_q[r][4] = s[r].phi;
+  }
+}
+
+// FP32C phase after step q of a block (q = 0..3) above the FP64 threshold:
+// the FP32 phase itself after the first three, the compensated pair after
+// the last (compared exactly in FP64 in both cases).
+__device__ __forceinline__ bool above_after_step(const float (&ph_q)[5], float e, int q,
+                                                 double th_rev) {
+  return q == 3 ? above_f64(ph_q[4], e, th_rev) : (double)ph_q[q + 1] > th_rev;
 }
 
 // FP32C threshold test of one slot's block: one compare on the largest phase,
 // and the exact FP64 test of each step only where an active lane came near
 // the threshold (a finished lane keeps its last phase until it takes a new
 // replica).
-__device__ __forceinline__ void threshold_f32(const float (&ph_q)[5], const float (&y_q)[4],
+__device__ __forceinline__ void threshold_f32(const float (&ph_q)[5], float e,
                                               float th_near_rev, double th_rev,
                                               uint64_t amask, uint64_t (&esc)[4]) {
   esc[0] = esc[1] = esc[2] = esc[3] = 0ull;
   const float top = fmaxf(fmaxf(ph_q[1], ph_q[2]), fmaxf(ph_q[3], ph_q[4]));
   if (__ballot(top > th_near_rev) & amask) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float ph = ph_q[q + 1];
-      // opaque copy: the error term is recomputed here, not kept live from
-      // the step (which would block the accumulate form there)
-      float y = y_q[q];
-      asm volatile("" : "+v"(y));
-      esc[q] = __ballot(ph > th_near_rev && above_f64(ph, kahan_error(y, ph, ph_q[q]), th_rev));
-    }
+    for (int q = 0; q < 4; ++q)
+      esc[q] = __ballot(ph_q[q + 1] > th_near_rev && above_after_step(ph_q, e, q, th_rev));
   }
 }
 
 // The same test for the lanes of one pass of a multi-set block: bit q of the
 // result is set where step q ends above the threshold.
-__device__ __forceinline__ uint32_t threshold_bits_f32(const float (&ph_q)[5],
-                                                       const float (&y_q)[4],
+__device__ __forceinline__ uint32_t threshold_bits_f32(const float (&ph_q)[5], float e,
                                                        float th_near_rev, double th_rev) {
   uint32_t bits = 0;
   const float top = fmaxf(fmaxf(ph_q[1], ph_q[2]), fmaxf(ph_q[3], ph_q[4]));
   if (__ballot(top > th_near_rev)) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float ph = ph_q[q + 1];
-      float y = y_q[q];
-      asm volatile("" : "+v"(y));
-      if (ph > th_near_rev && above_f64(ph, kahan_error(y, ph, ph_q[q]), th_rev))
-        bits |= 1u << q;
-    }
+    for (int q = 0; q < 4; ++q)
+      if (ph_q[q + 1] > th_near_rev && above_after_step(ph_q, e, q, th_rev)) bits |= 1u << q;
   }
   return bits;
 }
@@ -734,10 +741,10 @@ __device__ __forceinline__ void slice_body(const SliceArgs& a) {
               block_f64<MODEL, 1, MT, false>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, Q,
                                              nullptr, e1);
             } else {
-              float ph_q[1][5], y_q[1][4];
+              float ph_q[1][5];
               block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, Q, gQ,
-                                      ph_q, y_q);
-              threshold_f32(ph_q[0], y_q[0], Q.p.th_near_rev, Q.p.th_rev, amask[0], e1[0]);
+                                      ph_q);
+              threshold_f32(ph_q[0], s[0].e, Q.p.th_near_rev, Q.p.th_rev, amask[0], e1[0]);
             }
             finish_slot<false>(tab, a, s[0], amask[0], safe[0], e1[0], lane_bit, kInactive);
             if (amask[0] == 0 || blk + 1 >= a.blocks) break;
@@ -756,12 +763,11 @@ __device__ __forceinline__ void slice_body(const SliceArgs& a) {
         block_f64<MODEL, R, MT, false>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, P,
                                        nullptr, esc);
       } else {
-        float ph_q[R][5], y_q[R][4];
-        block_f32<MODEL, R, MT>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, P, gA, ph_q,
-                                y_q);
+        float ph_q[R][5];
+        block_f32<MODEL, R, MT>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, P, gA, ph_q);
 #pragma unroll
         for (int r = 0; r < R; ++r)
-          threshold_f32(ph_q[r], y_q[r], P.p.th_near_rev, P.p.th_rev, amask[r], esc[r]);
+          threshold_f32(ph_q[r], s[r].e, P.p.th_near_rev, P.p.th_rev, amask[r], esc[r]);
       }
     } else {
 #pragma unroll
@@ -783,10 +789,10 @@ __device__ __forceinline__ void slice_body(const SliceArgs& a) {
           } else {
             double gQ = Q.p.gA;
             asm volatile("" : "+v"(gQ));
-            float ph_q[5], y_q[4];
+            float ph_q[5];
             block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, r, &amask[r], &mc[r], &s[r],
-                                    Q, gQ, &ph_q, &y_q);
-            threshold_f32(ph_q, y_q, Q.p.th_near_rev, Q.p.th_rev, amask[r], esc[r]);
+                                    Q, gQ, &ph_q);
+            threshold_f32(ph_q, s[r].e, Q.p.th_near_rev, Q.p.th_rev, amask[r], esc[r]);
           }
         } else {
           // a lane is in the pass of set s0 exactly when its set is s0 (a
@@ -806,10 +812,10 @@ __device__ __forceinline__ void slice_body(const SliceArgs& a) {
               } else {
                 double gQ = Q.p.gA;
                 asm volatile("" : "+v"(gQ));
-                float ph_q[5], y_q[4];
+                float ph_q[5];
                 block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, r, &amask[r], &mc[r],
-                                        &s[r], Q, gQ, &ph_q, &y_q);
-                bits = threshold_bits_f32(ph_q, y_q, Q.p.th_near_rev, Q.p.th_rev);
+                                        &s[r], Q, gQ, &ph_q);
+                bits = threshold_bits_f32(ph_q, s[r].e, Q.p.th_near_rev, Q.p.th_rev);
               }
             }
             if (todo) ++extra_passes;
@@ -1290,17 +1296,25 @@ __global__ void trajectory_kernel(SetDev sd, uint64_t replica, int64_t n_steps,
     } else {
       const BoxMullerF32 bm = box_muller_f32(w);
       const BlockG gk = block_g4(P.p, s.kd, P.p.gA);
+      float d = s.e;
       for (int q = 0; q < 4 && k0 + q < n_steps; ++q) {
         const float zs = P.p.sig * bm.radius[q >> 1];
         const float trig = (q & 1) ? bm.s[q >> 1] : bm.c[q >> 1];
+        const float x = q == 0 ? s.phi : s.phi + d;
         if constexpr (MODEL == kUnderExplicit) {
-          step_f32_under(P.p, gk.g[q], zs, trig, s.phi, s.e, s.v);
+          step_f32_under(P.p, gk.g[q], zs, trig, x, d, s.v);
         } else if constexpr (MODEL == kUnderSemiImplicit) {
-          step_f32_under_si(P.p, gk.g[q], zs, trig, s.phi, s.e, s.v);
+          step_f32_under_si(P.p, gk.g[q], zs, trig, x, d, s.v);
         } else {
-          step_f32_over(P.p, gk.g[q], zs, trig, s.phi, s.e);
+          step_f32_over(P.p, gk.g[q], zs, trig, x, d);
         }
-        out_phi[k0 + q] = 2.0 * kPi * ((double)s.phi + (double)s.e);
+        // the phase the integrator tests after this step
+        if (q < 3) {
+          out_phi[k0 + q] = 2.0 * kPi * (double)(s.phi + d);
+        } else {
+          fold_advance(d, s.phi, s.e);
+          out_phi[k0 + q] = 2.0 * kPi * ((double)s.phi + (double)s.e);
+        }
         out_v[k0 + q] = (double)s.v;
       }
     }

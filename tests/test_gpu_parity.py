@@ -111,6 +111,21 @@ def test_trajectory_fp32c_tracks_fp64():
     assert np.abs(v32 - v64).max() < 2e-4
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_trajectory_crosses_at_the_recorded_step(prec):
+    # the trajectory kernel reports the phases the integrator tests: each
+    # replica's first phase above the threshold is at its recorded step
+    p = workloads.plain_escape(n_replicas=64, seed=11)
+    steps = _steps(api.simulate(p, prec, FIXED))
+    th = p["threshold"]
+    for i in range(8):
+        k = int(steps[i])
+        assert k > 0
+        phi, _ = api.trajectory(p, replica=i, n_steps=k, precision=prec)
+        assert (phi[:k - 1] <= th * (1 + 1e-12)).all(), i
+        assert phi[k - 1] > th * (1 - 1e-12), i
+
+
 # ---------------------------------------------------------------------------
 # escape steps, histograms, moments
 
