@@ -77,9 +77,11 @@ typedef enum { FPT_UNDERDAMPED = 0, FPT_OVERDAMPED = 1 } fpt_model;
 typedef enum { FPT_EXPLICIT = 0, FPT_SEMI_IMPLICIT = 1 } fpt_scheme;
 
 /* FPT_FP64: every replica operation in FP64 (the plain path).
- * FPT_FP32C: replica state in FP32 with Kahan-compensated phase accumulation;
- * FP64 is kept for gamma_k from the exact integer step and for the threshold
- * test near the threshold.  The same Philox words feed both. */
+ * FPT_FP32C: replica state in FP32 with a compensated phase (a float pair
+ * between 4-step blocks; each block's advance, summed in FP32, is added with
+ * Kahan's compensation); FP64 is kept for gamma_k from the exact integer
+ * step and for the threshold test near the threshold.  The same Philox words
+ * feed both. */
 typedef enum { FPT_FP64 = 0, FPT_FP32C = 1 } fpt_precision;
 
 /* Normal-number source.  FPT_RNG_PHILOX: the counter-based generator above.

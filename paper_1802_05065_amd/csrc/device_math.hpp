@@ -152,7 +152,7 @@ struct ParF64 {
 //   underdamped  v_k = damp v + G_k + nkS sin(2 pi phr) + sig z_k,
 //                phr_k = phr + h_rev v
 //   overdamped   phr_k = phr + G_k + nkS sin(2 pi phr) + sig z_k
-// (the phase sums Kahan-compensated once per block of 4 steps)
+// (the phase sum compensated once per block of 4 steps, see below)
 // with G_k = gA + gB k evaluated in FP64 from the exact step k, nkS = -kS,
 // and dG, dG2, dG3 the bias offsets of a block's steps 2, 3, 4 from its first.
 struct ParF32 {

@@ -64,7 +64,7 @@ struct Slot<false> {
   uint64_t idx, j;
   double kd;
   float phi, v;  // phi: phase in revolutions
-  float e;       // its Kahan error term: true phase = phi + e
+  float e;       // its error term: true phase = phi + e (between blocks)
 };
 
 // Constants of one set that the block loop reads, held in scalar registers:
