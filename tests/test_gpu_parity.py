@@ -111,16 +111,26 @@ def test_trajectory_fp32c_tracks_fp64():
     assert np.abs(v32 - v64).max() < 2e-4
 
 
+CROSSING_CASES = {
+    "explicit": lambda: workloads.plain_escape(n_replicas=64, seed=11),
+    "semi_implicit": lambda: dict(workloads.plain_escape(n_replicas=64, seed=12), scheme=1),
+    "overdamped": lambda: dict(workloads.uneven_overdamped(n_replicas=64, seed=13),
+                               max_steps=400_000, hist_k_max=400_000),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CROSSING_CASES))
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
-def test_trajectory_crosses_at_the_recorded_step(prec):
+def test_trajectory_crosses_at_the_recorded_step(prec, case):
     # the trajectory kernel reports the phases the integrator tests: each
     # replica's first phase above the threshold is at its recorded step
-    p = workloads.plain_escape(n_replicas=64, seed=11)
+    p = CROSSING_CASES[case]()
     steps = _steps(api.simulate(p, prec, FIXED))
     th = p["threshold"]
-    for i in range(8):
+    done = [i for i in range(64) if steps[i] > 0][:8]
+    assert len(done) == 8
+    for i in done:
         k = int(steps[i])
-        assert k > 0
         phi, _ = api.trajectory(p, replica=i, n_steps=k, precision=prec)
         assert (phi[:k - 1] <= th * (1 + 1e-12)).all(), i
         assert phi[k - 1] > th * (1 - 1e-12), i
