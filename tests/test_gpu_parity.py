@@ -111,6 +111,25 @@ def test_trajectory_fp32c_tracks_fp64():
     assert np.abs(v32 - v64).max() < 2e-4
 
 
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_noise_free_fp32c_tracks_fp64(scheme):
+    # T = 0: the underdamped FP32C velocity has no noise unit and the radii
+    # are zeroed; the deterministic path follows FP64, and every replica
+    # switches at the same step, within a few steps of FP64's
+    p = dict(workloads.switching_ramp(n_replicas=64), T=0.0, ramp=1e-4, scheme=scheme,
+             max_steps=210_000, hist_k_max=210_000)
+    phi32, v32 = api.trajectory(p, replica=5, n_steps=4000, precision="fp32c")
+    phi64, v64 = api.trajectory(p, replica=5, n_steps=4000, precision="fp64")
+    assert np.abs(phi32 - phi64).max() < 2e-4
+    assert np.abs(v32 - v64).max() < 2e-4
+    s32 = _steps(api.simulate(p, "fp32c", FIXED))
+    s64 = _steps(api.simulate(p, "fp64", FIXED))
+    assert (s64 > 0).all() and (s64 == s64[0]).all()
+    assert (s32 > 0).all() and (s32 == s32[0]).all()
+    print(f"noise-free switching step fp32c {s32[0]} fp64 {s64[0]}")
+    assert abs(int(s32[0]) - int(s64[0])) <= 200
+
+
 CROSSING_CASES = {
     "explicit": lambda: workloads.plain_escape(n_replicas=64, seed=11),
     "semi_implicit": lambda: dict(workloads.plain_escape(n_replicas=64, seed=12), scheme=1),
