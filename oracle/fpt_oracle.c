@@ -58,43 +58,53 @@ void oracle_rng_words(uint64_t seed, uint64_t replica, uint64_t block,
 }
 
 /* ---------------------------------------------------------------------- */
-/* Algorithm 2: the Mersenne Twister MT19937 (Matsumoto and Nishimura).
- * Initialization: mt[0] = seed, mt[i] = 1812433253 (mt[i-1] xor
- * (mt[i-1] >> 30)) + i.  Every 624 outputs the whole state is regenerated
- * (twist, with the 0x80000000 / 0x7fffffff split, offset 397 and the matrix
- * 0x9908b0df); each output is tempered by the shifts 11, 7, 15, 18 with the
- * masks 0x9d2c5680 and 0xefc60000.                                        */
+/* Algorithm 2's generator, MT19937 (Matsumoto and Nishimura, ACM TOMACS 8,
+ * 1998), taken straight from its defining linear recurrence over words of
+ * w = 32 bits with degree n = 624, middle distance m = 397, separation r = 31:
+ *   x_{k+n} = x_{k+m} xor A(upper bit of x_k | lower 31 bits of x_{k+1}),
+ *   A(y) = (y >> 1) xor (0x9908b0df if y is odd else 0),
+ * started from x_0 = seed, x_i = 1812433253 (x_{i-1} xor (x_{i-1} >> 30)) + i
+ * for i = 1 .. n-1.  Output number t (t = 0, 1, ...) is x_{n+t} passed through
+ * the tempering map (shifts 11, 7, 15, 18 with masks 0x9d2c5680 and
+ * 0xefc60000).  The state keeps the last n terms of the sequence; each call
+ * computes the next term from three of them, so no batch regeneration is
+ * needed.                                                                   */
+
+enum { MT_N = 624, MT_M = 397 };
 
 typedef struct {
-  uint32_t mt[624];
-  int index;
+  uint32_t x[MT_N]; /* x[t mod n] holds term t for the n most recent terms */
+  uint64_t k;       /* index of the oldest stored term */
 } mt_state;
 
 static void mt_seed(mt_state* s, uint32_t seed) {
-  s->mt[0] = seed;
-  for (int i = 1; i < 624; ++i)
-    s->mt[i] = 1812433253u * (s->mt[i - 1] ^ (s->mt[i - 1] >> 30)) + (uint32_t)i;
-  s->index = 624;
-}
-
-static void mt_twist(mt_state* s) {
-  for (int i = 0; i < 624; ++i) {
-    const uint32_t y = (s->mt[i] & 0x80000000u) | (s->mt[(i + 1) % 624] & 0x7fffffffu);
-    uint32_t next = s->mt[(i + 397) % 624] ^ (y >> 1);
-    if (y & 1u) next ^= 0x9908b0dfu;
-    s->mt[i] = next;
+  uint32_t prev = seed;
+  s->x[0] = seed;
+  for (uint32_t i = 1; i < MT_N; ++i) {
+    prev = 1812433253u * (prev ^ (prev >> 30)) + i;
+    s->x[i] = prev;
   }
-  s->index = 0;
+  s->k = 0;
 }
 
-static uint32_t mt_next(mt_state* s) {
-  if (s->index >= 624) mt_twist(s);
-  uint32_t y = s->mt[s->index++];
+static uint32_t mt_temper(uint32_t y) {
   y ^= y >> 11;
   y ^= (y << 7) & 0x9d2c5680u;
   y ^= (y << 15) & 0xefc60000u;
-  y ^= y >> 18;
-  return y;
+  return y ^ (y >> 18);
+}
+
+static uint32_t mt_next(mt_state* s) {
+  static const uint32_t odd_term[2] = {0u, 0x9908b0dfu};
+  const uint32_t xk = s->x[s->k % MT_N];
+  const uint32_t xk1 = s->x[(s->k + 1) % MT_N];
+  const uint32_t xkm = s->x[(s->k + MT_M) % MT_N];
+  const uint32_t y = (xk & 0x80000000u) | (xk1 & 0x7fffffffu);
+  const uint32_t next = xkm ^ (y >> 1) ^ odd_term[y & 1u];
+  /* term k + n replaces term k, which is no longer needed */
+  s->x[s->k % MT_N] = next;
+  s->k += 1;
+  return mt_temper(next);
 }
 
 void oracle_mt19937(uint32_t seed, uint64_t n, uint32_t* out) {
@@ -169,7 +179,11 @@ void oracle_derived(const oracle_params* p, double* sigma_out,
   } else {
     sigma = sqrt(2.0 * p->T * p->dt);
   }
-  const double phi0 = isnan(p->phi0) ? asin(p->gamma0) : p->phi0;
+  /* phi0 = the bottom of the well: arcsin(gamma) for Eq. (10), where V0
+   * multiplies the bias as well; arcsin(gamma / V0) for the overdamped
+   * potential -V0 cos(phi) - gamma phi */
+  const double well_sin = p->model == 0 ? p->gamma0 : p->gamma0 / p->V0;
+  const double phi0 = isnan(p->phi0) ? asin(well_sin) : p->phi0;
   const double v0 = isnan(p->v0) ? 0.0 : p->v0;
   /* th = pi - phi0: the top of the barrier of the tilted washboard */
   const double th = isnan(p->threshold) ? PI - phi0 : p->threshold;
@@ -188,7 +202,7 @@ void oracle_derived(const oracle_params* p, double* sigma_out,
  *   v_k   = v_{k-1} + h (-alpha v_{k-1} - V0 sin phi_{k-1} + V0 gamma_k)
  *           + sigma r_k
  * Both updates read the state of step k-1 (explicit Euler-Maruyama).
- * Overdamped (first-order analogue):
+ * Overdamped (first-order analogue, potential -V0 cos(phi) - gamma phi):
  *   phi_k = phi_{k-1} + h (-V0 sin phi_{k-1} + gamma_k) + sigma r_k
  * Escape: first k with phi_k > th (strict); none within max_steps -> -1.
  * r_k is normal number (k-1) mod 4 of block (k-1) div 4.                  */

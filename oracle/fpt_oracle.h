@@ -14,7 +14,11 @@
  *     scheme 1 replaces it by the semi-implicit (symplectic) Euler variant,
  *     v first and then phi with the new v (an extension, not in the paper);
  *     model 1 = overdamped washboard, the first-order analogue mentioned in
- *     Sect. II.B (the paper prints no algorithm for it).
+ *     Sect. II.B (the paper prints no algorithm for it):
+ *     phi' = -V0 sin(phi) + gamma + noise, potential -V0 cos(phi) - gamma phi,
+ *     whose well is at arcsin(gamma / V0); the NaN defaults of phi0 and of
+ *     the threshold (pi - phi0) follow it (V0 = 0 is the plain drift-diffusion
+ *     walk and needs explicit values).
  *   - noise amplitude D = alpha*T (Eq. (9): D = beta*theta with beta -> alpha,
  *     theta -> T); per-step noise sigma*r with sigma = sqrt(2*D*h) as in
  *     Algorithm 1.  Overdamped: sigma = sqrt(2*T*h).

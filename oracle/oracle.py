@@ -75,7 +75,7 @@ class _CMoments(ctypes.Structure):
 class OracleParams:
     """One parameter set.  ``model``: 0 underdamped, 1 overdamped.  NaN for
     phi0 / v0 / threshold selects the paper's defaults (arcsin(gamma0), 0,
-    pi - phi0)."""
+    pi - phi0; overdamped: arcsin(gamma0 / V0), the well of its potential)."""
 
     model: int = 0
     alpha: float = 0.1
