@@ -24,7 +24,8 @@
  *       phi_k = phi_{k-1} + dt v_{k-1}
  *       v_k   = v_{k-1} + dt (-alpha v_{k-1} - V0 sin phi_{k-1} + V0 gamma_k)
  *               + sqrt(2 alpha T dt) r_k
- *     Overdamped (first-order analogue, Sect. II.B):
+ *     Overdamped (first-order analogue, Sect. II.B; potential
+ *     -V0 cos(phi) - gamma phi):
  *       phi_k = phi_{k-1} + dt (-V0 sin phi_{k-1} + gamma_k) + sqrt(2 T dt) r_k
  *     with gamma_k = gamma0 + ramp*dt*k evaluated in FP64 from the integer k.
  *   - r_k is standard normal number (k-1) mod 4 of block (k-1) div 4 of the
@@ -101,7 +102,11 @@ typedef enum { FPT_RNG_PHILOX = 0, FPT_RNG_MT19937 = 1 } fpt_rng;
 typedef enum { FPT_SCHED_REFILL = 0, FPT_SCHED_ONE_PER_LANE = 1 } fpt_schedule;
 
 /* One parameter set ("job").  NaN phi0 / v0 / threshold select Algorithm 1's
- * defaults arcsin(gamma0), 0 and pi - phi0. */
+ * defaults: the bottom of the well at rest and the barrier top, phi0 =
+ * arcsin(gamma0), v0 = 0, threshold = pi - phi0.  For the overdamped model
+ * the well of -V0 cos(phi) - gamma phi is at arcsin(gamma0 / V0), which is
+ * the default phi0 there (the threshold stays pi - phi0).  A NaN phi0 needs
+ * |gamma0| <= 1 (underdamped) or V0 != 0 and |gamma0| <= |V0| (overdamped). */
 typedef struct fpt_params {
   int32_t model;        /* fpt_model */
   int32_t n_bins;       /* histogram bins, 1..FPT_MAX_BINS */
@@ -178,9 +183,10 @@ typedef struct fpt_server_s* fpt_server_t;
 
 /* ---- plans: a fixed batch of parameter sets ------------------------------ */
 
-/* Validate n_sets parameter sets (all of one model) and derive the per-set
- * constants of Algorithm 1 / 3's preamble: sigma = sqrt(2 alpha T dt)
- * (overdamped sqrt(2 T dt)), delta-gamma = ramp*dt, phi0, v0, threshold.
+/* Validate n_sets parameter sets (1 .. 2^20 - 1, all of one model) and
+ * derive the per-set constants of Algorithm 1 / 3's preamble:
+ * sigma = sqrt(2 alpha T dt) (overdamped sqrt(2 T dt)), delta-gamma =
+ * ramp*dt, phi0, v0, threshold.
  * tuning may be NULL (all fields autotuned).  Host-only; no device memory.
  * Errors: FPT_E_INVAL (message names the set and field). */
 fpt_status fpt_plan(const fpt_params* sets, int32_t n_sets, int32_t precision,
@@ -190,7 +196,12 @@ fpt_status fpt_plan(const fpt_params* sets, int32_t n_sets, int32_t precision,
  * allocates, 256-byte aligned, and may reuse it across calls). */
 fpt_status fpt_plan_workspace(fpt_plan_t plan, size_t* bytes);
 
-/* Run every replica of every set.  Asynchronous on `stream`.
+/* Run every replica of every set: the replica loop of Algorithm 1 (fixed
+ * bias) and Algorithm 3 (ramped bias) -- Euler steps from (phi0, v0) until
+ * phi > threshold, recording the step k (the escape time k*h, or the
+ * switching bias gamma_k) or -1 after max_steps -- with the replicas spread
+ * over persistent lanes as in Sect. III.B (one realization per thread, a
+ * finished thread takes the next one).  Asynchronous on `stream`.
  *   workspace : device, >= fpt_plan_workspace bytes
  *   out_steps : host array of n_sets device pointers (int64[n_replicas] each,
  *               entries may be NULL), or NULL: escape step per replica, -1 if
@@ -203,13 +214,18 @@ fpt_status fpt_simulate(fpt_plan_t plan, void* workspace,
                         void* stream);
 
 /* Copy set `set`'s histogram (n_bins counts) and moments of the last
- * fpt_simulate to host memory; synchronizes that call's stream.  Either
- * pointer may be NULL.  Errors: FPT_E_STATE before a simulate. */
+ * fpt_simulate to host memory: the escape-time histogram of Sect. II.B and
+ * the switching-current histogram / CDF of Sect. IV.B (bins over escape
+ * steps; gamma_k is monotone in k), and the mean first-passage time with
+ * its standard error that Sect. IV.A fits against the Kramers law.
+ * Synchronizes that call's stream.  Either pointer may be NULL.
+ * Errors: FPT_E_STATE before a simulate. */
 fpt_status fpt_histogram(fpt_plan_t plan, int32_t set, uint64_t* host_counts,
                          fpt_moments* host_m);
 
-/* Every set at once, with one device-to-host copy of the histograms and one
- * of the moments (plans of many sets):
+/* Every set at once (the same histograms and moments as fpt_histogram:
+ * Sect. II.B, IV.A, IV.B), with one device-to-host copy of the histograms and
+ * one of the moments (plans of many sets):
  *   host_counts : host uint64[sum of n_bins], sets in plan order, or NULL
  *   host_m      : host fpt_moments[n_sets], or NULL
  * Synchronizes the last fpt_simulate's stream.  Errors: FPT_E_STATE before
@@ -223,9 +239,12 @@ void fpt_plan_destroy(fpt_plan_t plan);
 
 /* ---- serving: jobs admitted continuously -------------------------------- */
 
-/* A request loop on its own host thread owns `stream` and the caller's
- * device pool (`pool_bytes` at `device_pool`, which must stay allocated until
- * fpt_server_destroy).  Jobs are admitted as set slots and pool memory free
+/* Continuous form of the streaming scheme of Sect. III.B (its three steps:
+ * integrate until the threshold, hand the escape time back, give the freed
+ * processor the next realization) for jobs, parameter sets that arrive over
+ * time.  A request loop on its own host thread owns `stream` and the
+ * caller's device pool (`pool_bytes` at `device_pool`, which must stay
+ * allocated until fpt_server_destroy).  Jobs are admitted as set slots and pool memory free
  * up; their replicas share the resident persistent lanes with the jobs
  * already running.  While every admitted replica has been drawn, the loop
  * packs the running ones into fewer lanes as they finish (tail compaction),
@@ -238,15 +257,20 @@ fpt_status fpt_server_create(void* device_pool, size_t pool_bytes,
                              const fpt_tuning* tuning, void* stream,
                              fpt_server_t* out);
 
-/* Queue one job (non-blocking, thread-safe).  FPT_E_NOMEM if the job could
- * never fit the pool, FPT_E_INVAL for bad parameters, FPT_E_BUSY if the
- * queue is full. */
+/* Queue one job: one parameter set whose replicas become new realizations
+ * for freed lanes (Sect. III.B, third step) once pool memory and a set slot
+ * are free (non-blocking, thread-safe).  FPT_E_NOMEM if the job could never
+ * fit the pool, FPT_E_INVAL for bad parameters, FPT_E_BUSY if the queue is
+ * full. */
 fpt_status fpt_submit(fpt_server_t server, const fpt_params* params,
                       uint64_t* job_id);
 
-/* FPT_PENDING while queued or running; FPT_OK once finished, filling
- * host_counts (n_bins), moments and the submit-to-finish latency (any may
- * be NULL).  A finished job is forgotten after its first FPT_OK. */
+/* Result of one job: the histogram and moments of its escape steps
+ * (Sect. II.B, IV.A, IV.B, as fpt_histogram), gathered from the escape times
+ * the lanes hand back (Sect. III.B, second step) once its last realization
+ * has finished.  FPT_PENDING while queued or running; FPT_OK once finished,
+ * filling host_counts (n_bins), moments and the submit-to-finish latency
+ * (any may be NULL).  A finished job is forgotten after its first FPT_OK. */
 fpt_status fpt_poll(fpt_server_t server, uint64_t job_id,
                     uint64_t* host_counts, fpt_moments* host_m,
                     double* latency_s);

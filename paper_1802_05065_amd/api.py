@@ -56,7 +56,8 @@ class Plan:
 
     def run(self, record_steps: bool = True, stream=None) -> SimResult:
         torch = _torch()
-        stream = stream or torch.cuda.current_stream(self.device)
+        current = torch.cuda.current_stream(self.device)
+        stream = stream or current
         steps = []
         ptrs = []
         for s in self.sets:
@@ -68,6 +69,14 @@ class Plan:
                 steps.append(None)
                 ptrs.append(0)
         hist = torch.empty(max(self.n_bins_total, 1), dtype=torch.int64, device=self.device)
+        if stream != current:
+            # the outputs (and the workspace) come from the caching allocator
+            # on the current stream: order the launch after whatever used that
+            # memory before, and keep it from being reused before the launch
+            # on `stream` is done
+            stream.wait_stream(current)
+            for t in [*(t for t in steps if t is not None), hist, self._ws_raw]:
+                t.record_stream(stream)
         _lib.fpt_simulate(self.handle, self.ws_ptr, ptrs, hist.data_ptr(), stream.cuda_stream)
         counts, moments = _lib.fpt_histogram_all(self.handle,
                                                  [int(s["n_bins"]) for s in self.sets])
@@ -97,6 +106,10 @@ class Server:
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         self._pool_raw, self.pool_ptr = _aligned_buffer(torch, pool_bytes, self.device)
         self.stream = torch.cuda.Stream(device=self.device)
+        # the pool was allocated on the current stream; the server writes it
+        # on its own stream from creation on
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._pool_raw.record_stream(self.stream)
         self.n_bins: Dict[int, int] = {}
         self.handle = _lib.fpt_server_create(self.pool_ptr, pool_bytes, precision, model,
                                              tuning, self.stream.cuda_stream)

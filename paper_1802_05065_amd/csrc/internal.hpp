@@ -19,6 +19,11 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kInactive = 0xFFFFFFFFu;
 constexpr int kChunk = 64;         // replicas per work-queue chunk
 constexpr int kBinBits = 12;       // FPT_MAX_BINS = 1 << kBinBits
+// Largest set count of a plan: every (set << kBinBits | bin) key, set index
+// up to kMaxPlanSets - 1, stays below kEmpty, the LDS tables' empty marker.
+constexpr int kMaxPlanSets = (1 << (32 - kBinBits)) - 1;
+static_assert((uint64_t(kMaxPlanSets - 1) << kBinBits | ((1u << kBinBits) - 1)) < kEmpty,
+              "histogram keys must not reach the empty marker");
 
 // Integrator kinds (the kernel's MODEL template argument): the two models of
 // fpt_model, plus the underdamped model with the semi-implicit scheme.

@@ -61,8 +61,13 @@ fpt_status validate_params(const fpt_params& p, int i) {
     return fail(FPT_E_INVAL, "set %d: V0, gamma0 and ramp must be finite", i);
   if (!finite_or_nan(p.phi0) || !finite_or_nan(p.v0) || !finite_or_nan(p.threshold))
     return fail(FPT_E_INVAL, "set %d: phi0, v0, threshold must be finite or NaN", i);
-  if (std::isnan(p.phi0) && !(p.gamma0 >= -1.0 && p.gamma0 <= 1.0))
+  if (std::isnan(p.phi0) && p.model == FPT_UNDERDAMPED && !(std::fabs(p.gamma0) <= 1.0))
     return fail(FPT_E_INVAL, "set %d: default phi0 = arcsin(gamma0) needs |gamma0| <= 1", i);
+  if (std::isnan(p.phi0) && p.model == FPT_OVERDAMPED &&
+      !(p.V0 != 0.0 && std::fabs(p.gamma0 / p.V0) <= 1.0))
+    return fail(FPT_E_INVAL,
+                "set %d: default phi0 = arcsin(gamma0 / V0) needs V0 != 0 and |gamma0| <= |V0|",
+                i);
   if (p.max_steps < 1 || p.max_steps > (int64_t(1) << 50))
     return fail(FPT_E_INVAL, "set %d: max_steps %lld outside [1, 2^50]", i,
                 (long long)p.max_steps);
@@ -94,7 +99,11 @@ SetDev derive_set(const fpt_params& p) {
   } else {
     s.sigma = std::sqrt(2.0 * p.T * p.dt);
   }
-  s.phi0 = std::isnan(p.phi0) ? std::asin(p.gamma0) : p.phi0;
+  // default start: the bottom of the well, arcsin(gamma0) for Eq. (10) (V0
+  // multiplies the bias too), arcsin(gamma0 / V0) for the overdamped
+  // potential -V0 cos(phi) - gamma phi
+  const double well_sin = p.model == FPT_UNDERDAMPED ? p.gamma0 : p.gamma0 / p.V0;
+  s.phi0 = std::isnan(p.phi0) ? std::asin(well_sin) : p.phi0;
   s.v0 = std::isnan(p.v0) ? 0.0 : p.v0;
   // default threshold: top of the washboard barrier, pi - arcsin(gamma)
   s.th = std::isnan(p.threshold) ? 3.14159265358979323846 - s.phi0 : p.threshold;
@@ -709,7 +718,10 @@ static double expected_steps(const fpt_params& q) {
 fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision,
                      const fpt_tuning* tuning, Plan** out) {
   if (!params || n_sets < 1) return fail(FPT_E_INVAL, "need at least one parameter set");
-  if (n_sets > (1 << 20)) return fail(FPT_E_INVAL, "at most 2^20 parameter sets");
+  // histogram keys are (set << 12 | bin) in 32 bits with 0xFFFFFFFF as the
+  // empty-slot marker: set 2^20 - 1 with bin 4095 would collide with it
+  if (n_sets > kMaxPlanSets)
+    return fail(FPT_E_INVAL, "at most %d parameter sets", kMaxPlanSets);
   if (precision != FPT_FP64 && precision != FPT_FP32C)
     return fail(FPT_E_INVAL, "precision %d is not FPT_FP64 or FPT_FP32C", precision);
   for (int32_t i = 0; i < n_sets; ++i) FPT_TRY(validate_params(params[i], i));

@@ -7,7 +7,8 @@ batched and serving mixes (numpy PCG64).  It holds none of the method's
 arithmetic and is shared by the tests (oracle side) and the GPU side.
 
 Field names follow ``fpt_params`` of ``include/fpt.h``; NaN for phi0 / v0 /
-threshold selects the paper's defaults (arcsin(gamma0), 0, pi - phi0).
+threshold selects the paper's defaults (arcsin(gamma0), 0, pi - phi0; the
+overdamped model starts at arcsin(gamma0 / V0), the well of its potential).
 """
 
 from __future__ import annotations

@@ -2,6 +2,7 @@
 include/fpt.h declares, and its host-side validation rejects bad input with
 the documented status codes."""
 
+import ctypes
 import math
 import os
 import re
@@ -164,3 +165,35 @@ def test_mt19937_plans(lib):
     with pytest.raises(_lib.FptError) as e:
         _lib.fpt_plan([p], "fp64", dict(replicas_per_lane=2))
     assert "one replica per lane" in e.value.message
+
+
+def test_plan_set_count_limit(lib):
+    # histogram keys pack (set << 12 | bin) into 32 bits below the LDS tables'
+    # empty marker 0xFFFFFFFF: 2^20 - 1 sets is the most a plan takes
+    one = _lib.make_params(workloads.plain_escape(n_replicas=1))
+    out = ctypes.c_void_p()
+    arr = (_lib.FptParams * (1 << 20))(*([one] * (1 << 20)))
+    st = lib.fpt_plan(arr, 1 << 20, _lib.FPT_FP64, None, ctypes.byref(out))
+    assert st == _lib.FPT_E_INVAL
+    assert b"parameter sets" in lib.fpt_last_error()
+    st = lib.fpt_plan(arr, (1 << 20) - 1, _lib.FPT_FP64, None, ctypes.byref(out))
+    assert st == _lib.FPT_OK
+    lib.fpt_plan_destroy(out)
+
+
+@pytest.mark.parametrize("model,gamma0,V0,ok", [
+    (0, 1.0, 1.0, True), (0, 1.01, 1.0, False), (0, 0.9, 0.5, True),
+    (1, 0.9, 0.5, False), (1, 1.5, 2.0, True), (1, 0.0, 0.0, False),
+])
+def test_default_start_needs_a_well(lib, model, gamma0, V0, ok):
+    # NaN phi0 means the bottom of the well: arcsin(gamma0) (Eq. (10)) or
+    # arcsin(gamma0 / V0) (overdamped), which must exist
+    maker = workloads.plain_escape if model == 0 else workloads.uneven_overdamped
+    p = dict(maker(n_replicas=4), gamma0=gamma0, V0=V0, phi0=math.nan, threshold=math.nan)
+    if ok:
+        _lib.fpt_plan_destroy(_lib.fpt_plan([p], "fp64"))
+    else:
+        with pytest.raises(_lib.FptError) as e:
+            _lib.fpt_plan([p], "fp64")
+        assert e.value.status == _lib.FPT_E_INVAL
+        assert "default phi0" in e.value.message
