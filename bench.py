@@ -124,23 +124,31 @@ def parse():
                     help="replicas of the oracle CPU-baseline sample (0: skip)")
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle processes (0: min(16, host cores))")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
-                    help="arrival window of the serving leg (0: skip)")
-    ap.add_argument("--serve-drain", type=float, default=60.0,
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="arrival window of the rate-scaled serving leg (0: skip)")
+    ap.add_argument("--serve-drain", type=float, default=45.0,
                     help="longest wait for admitted jobs after the window")
+    ap.add_argument("--literal-seconds", type=float, default=8.0,
+                    help="window of the serving trace at its literal 50 jobs/s (0: skip)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched leg (256 sets, full ramps) of the benchmark line")
     ap.add_argument("--serve-steps", type=int, default=0,
                     help="steps per launch of the serving loop (0: the server's default)")
     ap.add_argument("--serve-rho", type=float, default=0.7,
                     help="offered load of the rate-scaled trace, as a fraction of the "
                          "measured FP32C throughput")
-    ap.add_argument("--mode", choices=("switching", "uneven", "batched", "mt", "next"),
+    ap.add_argument("--mode", choices=("switching", "uneven", "batched", "mt", "next", "serve"),
                     default="switching",
                     help="switching: the benchmark line (default); uneven: refill vs "
                          "one-replica-per-lane on the uneven overdamped workload; batched: "
                          "the 256-set workload in one graph-replayed persistent launch; mt: "
                          "the switching workload with per-replica MT19937 against Philox; "
                          "next: rates of the semi-implicit scheme and of the Arrhenius and "
-                         "switching-distribution analyses")
+                         "switching-distribution analyses; serve: the serving legs alone, "
+                         "with --serve-seconds / --literal-seconds as given")
+    ap.add_argument("--capacity", type=float, default=1.43e12,
+                    help="serve mode: the FP32C replica-steps/s the rate-scaled trace is "
+                         "scaled to")
     ap.add_argument("--ramp-scale", type=float, default=1.0,
                     help="batched mode: multiply every ramp (shorter runs)")
     ap.add_argument("--no-regroup", action="store_true",
@@ -163,81 +171,134 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
 
 
-def cpu_baseline(n_rep: int, procs: int):
+def _host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except Exception:
+        return ""
+
+
+def _oracle_processes(tasks):
+    """Run the oracle CLI once per task (params dict, first replica, count),
+    all at once, one single-threaded process each.  Returns (replica-steps,
+    wall seconds, per-process seconds from the oracle's own clock)."""
     import oracle
     from paper_1802_05065_amd import workloads
 
     oracle.build(force=False)
-    p = workloads.switching_ramp(n_replicas=n_rep, seed=2)
-    op = oracle.OracleParams(**workloads.to_oracle_kwargs(p))
-    procs = max(1, min(procs, n_rep))
-    chunks = [(i * n_rep // procs, (i + 1) * n_rep // procs) for i in range(procs)]
     t0 = time.perf_counter()
     children = []
-    for a, b in chunks:
+    for p, first, n in tasks:
+        op = oracle.OracleParams(**workloads.to_oracle_kwargs(p))
         args = [oracle.oracle._CLI, str(op.model), repr(op.alpha), repr(op.T), repr(op.V0),
                 repr(op.gamma0), repr(op.ramp), repr(op.dt), repr(op.phi0), repr(op.v0),
-                repr(op.threshold), str(op.max_steps), str(op.seed), str(a), str(b - a)]
+                repr(op.threshold), str(op.max_steps), str(op.seed), str(first), str(n)]
         children.append(subprocess.Popen(args, stdout=subprocess.PIPE, text=True))
-    total = 0
+    total, secs = 0, []
     for c in children:
         out, _ = c.communicate()
         if c.returncode != 0:
             raise RuntimeError("oracle CLI failed")
-        total += int(out.split("\n")[0].split()[2])
-    wall = time.perf_counter() - t0
-    cpu = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-    except Exception:
-        pass
+        head = out.split("\n")[0].split()
+        total += int(head[2])
+        secs.append(float(head[4]))
+    return total, time.perf_counter() - t0, secs
+
+
+def cpu_baseline(n_rep: int, procs: int):
+    """The FP64 oracle on the host cores: the benchmark workload's first
+    `n_rep` replicas split over `procs` processes (the line's value), and
+    per-workload rates: the plain fixed-bias workload in full (one process),
+    16384 replicas of the uneven overdamped workload and one replica of each
+    of the batched workload's first 16 sets (16 processes each)."""
+    from paper_1802_05065_amd import workloads
+
+    procs = max(1, min(procs, n_rep))
+    p2 = workloads.switching_ramp(n_replicas=n_rep, seed=2)
+    tasks = [(p2, i * n_rep // procs, (i + 1) * n_rep // procs - i * n_rep // procs)
+             for i in range(procs)]
+    total, wall, secs = _oracle_processes(tasks)
+    cpu = _host_cpu_model()
+    per = {}
+
+    def record(name, tasks_, note):
+        rs, w, ss = _oracle_processes(tasks_)
+        per[name] = {"replica_steps": rs, "processes": len(tasks_), "wall_s": w,
+                     "replica_steps_per_s": rs / w,
+                     "ns_per_replica_step_one_core": 1e9 * sum(ss) / rs,
+                     "process_s_min": min(ss), "sample": note}
+
+    record("plain_escape_full", [(workloads.plain_escape(), 0, 1024)],
+           "fixed-bias workload, all 1024 replicas, one process")
+    p3 = workloads.uneven_overdamped(n_replicas=16384)
+    record("uneven_16384", [(p3, i * 1024, 1024) for i in range(16)],
+           "uneven overdamped workload, replicas 0..16383, 16 processes of 1024")
+    sets = workloads.batched_sets(n_sets=256, seed=4)
+    record("batched_16_sets", [(s, 0, 1) for s in sets[:16]],
+           "batched workload, replica 0 of sets 0..15, one process each")
     return {"value": total / wall, "unit": "replica-steps/s", "cores": procs, "kind": "oracle",
             "sample": f"switching-current workload, replicas 0..{n_rep - 1} (seed 2) in "
                       f"{procs} single-threaded oracle processes, {total} replica-steps, "
-                      f"{wall:.1f} s wall; host CPU: {cpu}"}
+                      f"{wall:.1f} s wall (each process {min(secs):.1f}-{max(secs):.1f} s)",
+            "ns_per_replica_step_one_core": 1e9 * sum(secs) / total,
+            "host_cores": os.cpu_count(), "host_cpu": cpu, "per_workload": per}
 
 
 def serving_leg(capacity: float, window_s: float, drain_s: float, rho: float,
-                steps_per_launch: int = 0):
-    """Continuous batching: the serving trace (Poisson arrivals at 50 jobs/s,
-    ramp jobs with 2^10..2^18 replicas) offered at `rho` of the measured
-    capacity by stretching its arrival times; jobs arriving in `window_s` are
-    submitted to an fpt server and polled until done (at most `drain_s` more).
-    Latency is submit-to-result."""
+                steps_per_launch: int = 0, literal: bool = False):
+    """Continuous batching on the serving trace (Poisson arrivals at 50
+    jobs/s, ramp jobs with 2^10..2^18 replicas).  Rate-scaled (default): the
+    arrival times are stretched so the trace offers `rho` of the measured
+    capacity; jobs arriving in `window_s` are submitted and polled until done
+    (at most `drain_s` more).  Literal: the trace at 50 jobs/s as written for
+    `window_s`, then stop; what finished, and the backlog left.  Latency is
+    submit-to-result; it is also given per unit of the job's own work
+    (seconds per 10^12 replica-steps) and as a stretch (latency x capacity /
+    work: 1 is a job that had the whole GPU's rate to itself)."""
     import numpy as np
     import torch
 
     from paper_1802_05065_amd import _lib, workloads
 
     trace = workloads.serving_trace(rate_per_s=50.0, duration_s=60.0, seed=5)
-    # work of a job, bounded by the steps to gamma = 1 (hist_k_max)
+    # expected work of a job, bounded by the steps to gamma = 1 (hist_k_max)
     work = np.array([j["params"]["n_replicas"] * j["params"]["hist_k_max"] for j in trace],
                     dtype=np.float64)
     mean_work = float(work.mean())
-    lam = rho * capacity / mean_work
+    lam = 50.0 if literal else rho * capacity / mean_work
     stretch = 50.0 / lam
     pool_bytes = 1 << 30
     pool = torch.empty(pool_bytes + 256, dtype=torch.uint8, device="cuda")
     base = pool.data_ptr() + (-pool.data_ptr()) % 256
     stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
     tun = dict(steps_per_launch=steps_per_launch) if steps_per_launch else None
     srv = _lib.fpt_server_create(base, pool_bytes, "fp32c", 0, tun, stream.cuda_stream)
-    pending, lat = {}, []
+    pending, lat, per_work, stretch_f, t_sub = {}, [], [], [], {}
     i = 0
     t0 = time.perf_counter()
     try:
         while True:
             now = time.perf_counter() - t0
             while i < len(trace) and trace[i]["t"] * stretch <= min(now, window_s):
-                pending[_lib.fpt_submit(srv, trace[i]["params"])] = trace[i]["params"]
+                jid = _lib.fpt_submit(srv, trace[i]["params"])
+                pending[jid] = trace[i]["params"]
+                t_sub[jid] = time.perf_counter() - t0
                 i += 1
             for jid in list(pending):
-                r = _lib.fpt_poll(srv, jid, pending[jid]["n_bins"])
+                p = pending[jid]
+                r = _lib.fpt_poll(srv, jid, p["n_bins"])
                 if r is not None:
+                    m = r[1]
+                    w = m["sum_k"] + m["n_censored"] * p["max_steps"]
                     lat.append(r[2])
+                    per_work.append(r[2] / (w / 1e12))
+                    stretch_f.append(r[2] * capacity / w)
                     del pending[jid]
             arrivals_done = i >= len(trace) or trace[i]["t"] * stretch > window_s
+            if literal and now >= window_s:
+                break
             if (now >= window_s and arrivals_done and not pending) or now > window_s + drain_s:
                 break
             time.sleep(0.002)
@@ -245,20 +306,36 @@ def serving_leg(capacity: float, window_s: float, drain_s: float, rho: float,
         st = _lib.fpt_server_stats_get(srv)
     finally:
         _lib.fpt_server_destroy(srv)
-    lat = np.array(lat)
-    return {
-        "trace": "serving mix (Poisson, 2^10..2^18 replicas, ramp jobs) offered at "
-                 f"rho={rho} of the measured FP32C capacity",
+    lat, per_work, stretch_f = np.array(lat), np.array(per_work), np.array(stretch_f)
+
+    def pct(a, q):
+        return float(np.percentile(a, q)) if a.size else None
+
+    out = {
         "offered_jobs_per_s": lam, "window_s": window_s, "submitted": i,
         "finished": int(lat.size), "unfinished": len(pending),
-        "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
-        "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
+        "p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "max_s": float(lat.max()) if lat.size else None,
+        "p50_s_per_1e12_replica_steps": pct(per_work, 50),
+        "p99_s_per_1e12_replica_steps": pct(per_work, 99),
+        "p50_stretch": pct(stretch_f, 50), "p99_stretch": pct(stretch_f, 99),
         "replica_steps_per_s": st["replica_steps"] / elapsed, "launches": st["n_launches"],
-        "literal_trace": {"jobs_per_s": 50.0, "offered_replica_steps_per_s": 50.0 * mean_work,
-                          "rho": 50.0 * mean_work / capacity,
-                          "note": "the literal trace offers more work than one GPU can "
-                                  "integrate, so its queue grows without bound"},
+        "elapsed_s": elapsed,
     }
+    if literal:
+        out.update({"trace": "serving trace as written: Poisson arrivals at 50 jobs/s, ramp "
+                             "jobs with 2^10..2^18 replicas, stopped at the end of the window",
+                    "offered_replica_steps_per_s": 50.0 * mean_work,
+                    "rho": 50.0 * mean_work / capacity,
+                    "backlog_jobs": i - int(lat.size),
+                    "queued_at_stop": st["queued"], "running_at_stop": st["running"]})
+    else:
+        out["trace"] = ("serving mix (Poisson, 2^10..2^18 replicas, ramp jobs) offered at "
+                        f"rho={rho} of the measured FP32C capacity")
+        if pending:
+            # jobs still running at the drain cap: their latency is at least
+            # their age then (lower bounds, not in the percentiles)
+            out["unfinished_age_s"] = sorted(round(elapsed - t_sub[j], 2) for j in pending)
+    return out
 
 
 def uneven_mode(args):
@@ -506,6 +583,77 @@ def next_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def batched_leg():
+    """The batched workload (256 ramp sets, 5.7e6 replicas, full ramps) in
+    one FP32C plan: the multi-set kernel with its regroups, autotuned (the
+    tuner's trials run first on the same plan with a 20000-step cap,
+    untimed).  Whole-run rate, kernel rate and the kernel's roofline terms."""
+    import torch
+
+    from paper_1802_05065_amd import api, workloads
+
+    sets = workloads.batched_sets(n_sets=256, seed=4)
+    api.simulate([dict(x, max_steps=min(x["max_steps"], 20_000),
+                       hist_k_max=min(x["hist_k_max"] or x["max_steps"], 20_000))
+                  for x in sets], "fp32c", None, record_steps=False)
+    plan = api.Plan(sets, "fp32c", None)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = plan.run(record_steps=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    finally:
+        plan.close()
+    st = r.stats
+    roof = batched_roofline(st)
+    if roof is not None:
+        roof["kernel"] = "slice_kernel<fp32c, underdamped, multi-set>"
+        roof["avg_launch_ms"] = st["kernel_ms"] / max(st["n_launches"], 1)
+    return {"workload": "batched: 256 ramp sets (alpha log-uniform [0.01, 1], T uniform "
+                        "[1e-3, 5e-2], ramp log-uniform [1e-7, 1e-4]), 2^12..2^16 replicas each, "
+                        "dt 0.05, FP32C, one plan",
+            "replicas": sum(s["n_replicas"] for s in sets),
+            "replica_steps": st["replica_steps"], "wall_s": t1 - t0,
+            "replica_steps_per_s": st["replica_steps"] / (t1 - t0),
+            "kernel_replica_steps_per_s": st["replica_steps"] / (st["kernel_ms"] * 1e-3)
+            if st["kernel_ms"] > 0 else None,
+            "launches": st["n_launches"], "regroups": st["n_regroups"],
+            "compactions": st["n_compactions"],
+            "lane_utilization": st["replica_steps"] / max(st["lane_steps"], 1),
+            "extra_pass_fraction": st["extra_passes"] / max(st["lane_steps"] / 256, 1),
+            "censored": int(sum(m["n_censored"] for m in r.moments)),
+            "tuning": st["tuning"], "roofline": roof}
+
+
+def serving_legs(args, capacity):
+    """The rate-scaled serving trace and the literal one, as the arguments
+    ask (None when both are off)."""
+    out = None
+    if args.serve_seconds > 0:
+        out = serving_leg(capacity, args.serve_seconds, args.serve_drain, args.serve_rho,
+                          args.serve_steps)
+        print(f"[bench] serving: {out['finished']} jobs, p50 {out['p50_s']} s, "
+              f"p99 {out['p99_s']} s", file=sys.stderr, flush=True)
+    if args.literal_seconds > 0:
+        lit = serving_leg(capacity, args.literal_seconds, 0.0, args.serve_rho, args.serve_steps,
+                          literal=True)
+        print(f"[bench] literal trace: {lit['finished']} of {lit['submitted']} jobs done, "
+              f"backlog {lit['backlog_jobs']}", file=sys.stderr, flush=True)
+        out = dict(out or {}, literal_trace=lit)
+    return out
+
+
+def serve_mode(args):
+    """The serving legs alone, against the capacity the benchmark line
+    measured (`--capacity`, default 1.43e12 replica-steps/s)."""
+    import torch
+
+    torch.cuda.set_device(0)
+    out = serving_legs(args, args.capacity)
+    print(json.dumps({"capacity": args.capacity, "latency": out}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -527,6 +675,9 @@ def main():
     if args.mode == "next":
         next_mode(args)
         return
+    if args.mode == "serve":
+        serve_mode(args)
+        return
     import numpy as np
     import torch
     from scipy import stats
@@ -547,13 +698,17 @@ def main():
 
     p32 = workloads.switching_ramp(n_replicas=args.replicas, seed=2)
     plan32 = api.Plan([p32], "fp32c", None, dev)
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         plan32.run()
+        print(f"[bench] warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        # each run ends synchronized (its histogram readback); the progress
+        # line costs microseconds of a multi-second step
         runs.append(plan32.run())
+        print(f"[bench] step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rs32 = sum(r.stats["replica_steps"] for r in runs)
@@ -585,17 +740,24 @@ def main():
               "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s",
               "frac": f64_kernel * FP64_FLOPS_PER_STEP / PEAK_FP64_FLOPS,
               "flops_per_replica_step": FP64_FLOPS_PER_STEP}
-    # same-seed paired error of FP32C against FP64 on the first 2^14 replicas
-    n_pair = min(2 ** 14, args.replicas)
-    pair64 = api.simulate(workloads.switching_ramp(n_replicas=n_pair, seed=2), "fp64")
-    k64 = pair64.steps[0].cpu().numpy()
-    k32 = steps32[:n_pair]
-    both = (k64 > 0) & (k32 > 0)
-    dk = np.abs(k32[both] - k64[both]).astype(np.float64)
-    paired = {"replicas": n_pair, "identical_fraction": float(np.mean(k32 == k64)),
-              "mean_abs_dk_steps": float(dk.mean()) if dk.size else None,
-              "max_abs_dk_steps": float(dk.max()) if dk.size else None,
-              "max_abs_dgamma_sw": float(dk.max() * p64["ramp"] * p64["dt"]) if dk.size else None}
+    # same-seed paired error of FP32C against FP64: the FP64 oracle's
+    # switching steps of the first 1024 replicas (seed 2), stored by
+    # tests/golden/make_switching_golden.py
+    paired = None
+    gold_path = os.path.join(ROOT, "tests", "golden", "switching_fp64_seed2_first1024.json")
+    if args.replicas >= 1024 and os.path.exists(gold_path):
+        k64 = np.array(json.load(open(gold_path))["escape_steps"], dtype=np.int64)
+        k32 = steps32[:k64.size]
+        both = (k64 > 0) & (k32 > 0)
+        dk = np.abs(k32[both] - k64[both]).astype(np.float64)
+        paired = {"replicas": int(k64.size), "reference": "FP64 oracle, same seed",
+                  "identical_fraction": float(np.mean(k32 == k64)),
+                  "mean_abs_dk_steps": float(dk.mean()) if dk.size else None,
+                  "median_abs_dk_steps_of_differing": float(np.median(dk[dk > 0]))
+                  if (dk > 0).any() else 0.0,
+                  "max_abs_dk_steps": float(dk.max()) if dk.size else None,
+                  "max_abs_dgamma_sw": float(dk.max() * p64["ramp"] * p64["dt"])
+                  if dk.size else None}
     print(f"[bench] fp64 {args.fp64_replicas} replicas: {value64:.4e} replica-steps/s",
           file=sys.stderr, flush=True)
 
@@ -609,6 +771,12 @@ def main():
                "mean_diff_over_se": dmean / se if se > 0 else None,
                "censored_fp32c": int((steps32 < 0).sum()), "censored_fp64": int((steps64 < 0).sum())}
 
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def lanes_of(tun):
+        return cus * 4 * tun["waves_per_simd"] * 64 * tun["replicas_per_lane"]
+
+    lanes32, lanes64 = lanes_of(st["tuning"]), lanes_of(r64.stats["tuning"])
     kernel_s = st["kernel_ms"] * 1e-3
     launches = max(st["n_launches"], 1)
     achieved = st["replica_steps"] * OPS_FP32C / kernel_s if kernel_s > 0 else 0.0
@@ -622,12 +790,13 @@ def main():
                                        if kernel_s > 0 and mix_attainable() else None),
             "avg_launch_ms": st["kernel_ms"] / launches, "launches": st["n_launches"]}
 
-    latency = None
-    if args.serve_seconds > 0:
-        latency = serving_leg(value, args.serve_seconds, args.serve_drain, args.serve_rho,
-                              args.serve_steps)
-        print(f"[bench] serving: {latency['finished']} jobs, p50 {latency['p50_s']} s, "
-              f"p99 {latency['p99_s']} s", file=sys.stderr, flush=True)
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg()
+        print(f"[bench] batched: {batched['replica_steps_per_s']:.4e} replica-steps/s, "
+              f"{batched['launches']} launches", file=sys.stderr, flush=True)
+
+    latency = serving_legs(args, value)
 
     cpu = None
     if args.cpu_replicas > 0:
@@ -645,11 +814,16 @@ def main():
                    "tuning": st["tuning"]},
         "kernel_value": st["replica_steps"] / kernel_s if kernel_s > 0 else None,
         "fp64": {"value": value64, "replicas": args.fp64_replicas,
+                 "lanes": lanes64,
+                 "note": "independent seed (3); the FP64 leg's replicas take "
+                         f"{args.fp64_replicas / lanes64:.2f} rounds of its lanes, the FP32C "
+                         f"leg's {args.replicas / lanes32:.2f}",
                  "kernel_value": f64_kernel,
                  "speedup_fp32c_over_fp64": value / value64 if value64 > 0 else None,
                  "tuning": r64.stats["tuning"], "roofline": roof64},
         "ks": ks_info,
         "paired_error_vs_fp64": paired,
+        "batched": batched,
         "latency": latency,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define FPT_API_VERSION 1
+#define FPT_API_VERSION 2
 #define FPT_MAX_BINS 4096
 
 typedef enum {
@@ -250,10 +250,16 @@ void fpt_plan_destroy(fpt_plan_t plan);
  * packs the running ones into fewer lanes as they finish (tail compaction),
  * which speeds up each remaining replica; an admission restores the full
  * width.  While replicas wait, each launch is followed by a regroup into set
- * order as for plans (tuning->no_regroup).  Errors: FPT_E_NOMEM if the pool
- * cannot hold the fixed lane state. */
+ * order as for plans (tuning->no_regroup).  Every job of a server shares its
+ * model and scheme (fpt_scheme: explicit, or semi-implicit for the
+ * underdamped model), since every launch runs one integrator.  Pool memory
+ * beyond the fixed lane state holds the work ring (at least 4096 chunks of
+ * 64 replicas, up to half the rest) and the jobs' histograms (the rest); a
+ * job is admitted once a set slot, ring room for its replicas and room for
+ * its bins are free.  Errors: FPT_E_NOMEM if the pool cannot hold the fixed
+ * lane state, the minimal ring and FPT_MAX_BINS bins. */
 fpt_status fpt_server_create(void* device_pool, size_t pool_bytes,
-                             int32_t precision, int32_t model,
+                             int32_t precision, int32_t model, int32_t scheme,
                              const fpt_tuning* tuning, void* stream,
                              fpt_server_t* out);
 

@@ -144,7 +144,8 @@ SIGNATURES = [
     ("fpt_plan_stats", ctypes.c_int, [_VP, ctypes.POINTER(FptRunStats)]),
     ("fpt_plan_destroy", None, [_VP]),
     ("fpt_server_create", ctypes.c_int, [_VP, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
-                                         ctypes.POINTER(FptTuning), _VP, ctypes.POINTER(_VP)]),
+                                         ctypes.c_int32, ctypes.POINTER(FptTuning), _VP,
+                                         ctypes.POINTER(_VP)]),
     ("fpt_submit", ctypes.c_int, [_VP, ctypes.POINTER(FptParams),
                                   ctypes.POINTER(ctypes.c_uint64)]),
     ("fpt_poll", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
@@ -288,10 +289,10 @@ def fpt_plan_destroy(plan: int) -> None:
 
 
 def fpt_server_create(pool: int, pool_bytes: int, precision, model: int,
-                      tuning: Optional[Dict], stream: Optional[int]) -> int:
+                      tuning: Optional[Dict], stream: Optional[int], scheme: int = 0) -> int:
     t = make_tuning(tuning)
     out = ctypes.c_void_p()
-    check(lib().fpt_server_create(pool, pool_bytes, precision_code(precision), model,
+    check(lib().fpt_server_create(pool, pool_bytes, precision_code(precision), model, scheme,
                                   ctypes.byref(t) if t is not None else None, stream or None,
                                   ctypes.byref(out)))
     return out.value

@@ -93,36 +93,73 @@ def fulton_dunkleberger_cdf(gamma_grid, alpha: float, T: float, ramp: float,
     return 1.0 - np.exp(-np.interp(np.minimum(grid, top), u, cum) / ramp)
 
 
+def barrier_fits(temperatures, tau, se=None) -> Dict:
+    """Barrier heights from mean first-passage times over temperatures:
+    the slope of ln<tau> against 1/T (the Arrhenius law, Eq. (13)) and the
+    slope of ln(T <tau>) against 1/T (the prefactor form of Eq. (14), read
+    as the quasipotential estimate of Eq. (15)), each a least-squares line
+    weighted by 1 / var(ln tau) when standard errors are given, with the
+    slope's standard error."""
+    T = np.asarray(temperatures, dtype=np.float64)
+    tau = np.asarray(tau, dtype=np.float64)
+    x = 1.0 / T
+    w = np.ones_like(tau) if se is None else (tau / np.asarray(se, dtype=np.float64)) ** 2
+    out = {}
+    for name, y in (("arrhenius", np.log(tau)), ("kramers_form", np.log(T * tau))):
+        W = w.sum()
+        xm, ym = (w * x).sum() / W, (w * y).sum() / W
+        sxx = (w * (x - xm) ** 2).sum()
+        slope = (w * (x - xm) * (y - ym)).sum() / sxx
+        out[f"delta_U_{name}"] = float(slope)
+        # with known variances 1/w of the points, var(slope) = 1 / sxx
+        out[f"delta_U_{name}_se"] = float(math.sqrt(1.0 / sxx)) if se is not None else None
+    return out
+
+
 def arrhenius_sweep(gamma: float, alpha: float, temperatures: Sequence[float],
                     n_replicas: int = 4096, dt: float = 0.02, V0: float = 1.0,
                     precision: str = "fp32c", seed: int = 100,
-                    max_steps: Optional[int] = None, scheme: int = 0) -> Dict:
-    """Mean first-passage time (to phi0 + 2 pi from the well bottom) at each
-    temperature, in one batched plan, and the barrier fitted from it."""
+                    max_steps: Optional[int] = None, scheme: int = 0,
+                    threshold: str = "period", record_steps: bool = False) -> Dict:
+    """Mean first-passage time from the well bottom at each temperature, in
+    one batched plan, and the barrier fitted from it (``barrier_fits``), beside
+    the same fits of the moderate-damping Kramers times at those
+    temperatures.  ``threshold``: "period" escapes at phi0 + 2 pi (the next
+    well); "barrier" uses Algorithm 1's own criterion, NaN start and
+    threshold (at rest in the well, escape past the barrier top
+    pi - arcsin(gamma)).  ``record_steps`` adds every set's escape steps
+    (host int64 arrays) as "steps"."""
     phi0 = math.asin(gamma)
     temps = [float(t) for t in temperatures]
     du = float(barrier_height(gamma, V0))
+    if threshold == "period":
+        start = dict(phi0=phi0, v0=0.0, threshold=phi0 + 2.0 * math.pi)
+    elif threshold == "barrier":
+        start = dict(phi0=math.nan, v0=math.nan, threshold=math.nan)
+    else:
+        raise ValueError(f"threshold {threshold!r}: 'period' or 'barrier'")
     sets = []
     for i, T in enumerate(temps):
         tau_est = 1.0 / float(kramers_rate(gamma, alpha, T, V0))
         cap = max_steps or int(min(2 ** 40, 40 * tau_est / dt + 1e5))
         sets.append(workloads.base_params(
             model=workloads.UNDERDAMPED, alpha=alpha, T=T, V0=V0, gamma0=gamma, ramp=0.0,
-            dt=dt, phi0=phi0, v0=0.0, threshold=phi0 + 2.0 * math.pi, max_steps=cap,
-            seed=seed + i, n_replicas=n_replicas, n_bins=64, hist_k_max=cap) | {"scheme": scheme})
-    res = api.simulate(sets, precision, record_steps=False)
+            dt=dt, max_steps=cap, seed=seed + i, n_replicas=n_replicas, n_bins=64,
+            hist_k_max=cap, **start) | {"scheme": scheme})
+    res = api.simulate(sets, precision, record_steps=record_steps)
     tau = np.array([m["mean_t"] for m in res.moments])
     se = np.array([m["se_t"] for m in res.moments])
     cens = [int(m["n_censored"]) for m in res.moments]
-    inv_t = 1.0 / np.array(temps)
-    w = (tau / se) ** 2  # weights of ln(tau): 1 / var(ln tau)
-    arr = np.polyfit(inv_t, np.log(tau), 1, w=np.sqrt(w))
-    kra = np.polyfit(inv_t, np.log(np.array(temps) * tau), 1, w=np.sqrt(w))
+    steps = [s.cpu().numpy() for s in res.steps] if record_steps else None
+    tau_k = [1.0 / float(kramers_rate(gamma, alpha, T, V0)) for T in temps]
+    fits = barrier_fits(temps, tau, se)
+    theory = barrier_fits(temps, tau_k, np.array(tau_k) * se / tau)
     return {"temperatures": temps, "mean_fpt": tau.tolist(), "se": se.tolist(),
-            "censored": cens, "delta_U": du,
-            "delta_U_arrhenius": float(arr[0]), "delta_U_kramers_form": float(kra[0]),
-            "kramers_tau": [1.0 / float(kramers_rate(gamma, alpha, T, V0)) for T in temps],
-            "stats": res.stats}
+            "censored": cens, "delta_U": du, **fits,
+            "kramers_tau": tau_k,
+            "theory_delta_U_arrhenius": theory["delta_U_arrhenius"],
+            "theory_delta_U_kramers_form": theory["delta_U_kramers_form"],
+            "sets": sets, "steps": steps, "stats": res.stats}
 
 
 def switching_distribution(alpha: float, T: float, ramp: float, n_replicas: int = 30000,

@@ -101,7 +101,7 @@ class Server:
     else (counts, moments, latency_s)."""
 
     def __init__(self, precision="fp32c", model: int = 0, tuning: Optional[Dict] = None,
-                 pool_bytes: int = 1 << 30, device=None):
+                 pool_bytes: int = 1 << 30, device=None, scheme: int = 0):
         torch = _torch()
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         self._pool_raw, self.pool_ptr = _aligned_buffer(torch, pool_bytes, self.device)
@@ -112,7 +112,7 @@ class Server:
         self._pool_raw.record_stream(self.stream)
         self.n_bins: Dict[int, int] = {}
         self.handle = _lib.fpt_server_create(self.pool_ptr, pool_bytes, precision, model,
-                                             tuning, self.stream.cuda_stream)
+                                             tuning, self.stream.cuda_stream, scheme)
 
     def submit(self, params: Dict) -> int:
         job = _lib.fpt_submit(self.handle, params)

@@ -453,8 +453,8 @@ struct fpt_server_s {
 extern "C" {
 
 fpt_status fpt_server_create(void* device_pool, size_t pool_bytes, int32_t precision,
-                             int32_t model, const fpt_tuning* tuning, void* stream,
-                             fpt_server_t* out) {
+                             int32_t model, int32_t scheme, const fpt_tuning* tuning,
+                             void* stream, fpt_server_t* out) {
   if (!out) return fpt::fail(FPT_E_INVAL, "out is NULL");
   *out = nullptr;
   if (!device_pool) return fpt::fail(FPT_E_INVAL, "device_pool is NULL");
@@ -464,11 +464,18 @@ fpt_status fpt_server_create(void* device_pool, size_t pool_bytes, int32_t preci
     return fpt::fail(FPT_E_INVAL, "precision %d unknown", precision);
   if (model != FPT_UNDERDAMPED && model != FPT_OVERDAMPED)
     return fpt::fail(FPT_E_INVAL, "model %d unknown", model);
+  if (scheme != FPT_EXPLICIT && scheme != FPT_SEMI_IMPLICIT)
+    return fpt::fail(FPT_E_INVAL, "scheme %d unknown", scheme);
+  if (model == FPT_OVERDAMPED && scheme != FPT_EXPLICIT)
+    return fpt::fail(FPT_E_INVAL, "the overdamped model has only scheme 0");
+  fpt_params kind{};
+  kind.model = model;
+  kind.scheme = scheme;
   auto* s = new fpt::Server();
   s->pool = static_cast<char*>(device_pool);
   s->pool_bytes = pool_bytes;
   s->precision = precision;
-  s->model = model;
+  s->model = fpt::integrator_kind(kind);  // the one integrator every launch runs
   if (tuning) s->tuning = *tuning;
   if (s->tuning.steps_per_launch < 0 || s->tuning.steps_per_launch % 4 ||
       s->tuning.replicas_per_lane < 0 || s->tuning.replicas_per_lane > 2 ||
@@ -495,9 +502,9 @@ fpt_status fpt_submit(fpt_server_t server, const fpt_params* params, uint64_t* j
   FPT_TRY(fpt::validate_params(*params, 0));
   if (params->rng != FPT_RNG_PHILOX)
     return fpt::fail(FPT_E_INVAL, "the server runs Philox jobs only (rng 0)");
-  if (params->model != s->model || params->scheme != FPT_EXPLICIT)
-    return fpt::fail(FPT_E_INVAL, "job model %d / scheme %d: this server runs model %d with "
-                     "the explicit scheme", params->model, params->scheme, s->model);
+  if (fpt::integrator_kind(*params) != s->model)
+    return fpt::fail(FPT_E_INVAL, "job model %d / scheme %d: this server runs another "
+                     "model or scheme", params->model, params->scheme);
   const uint64_t n_chunks =
       ((uint64_t)params->n_replicas + fpt::kChunk - 1) / (uint64_t)fpt::kChunk;
   std::lock_guard<std::mutex> lk(s->mu);

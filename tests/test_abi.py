@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version(lib):
-    assert _lib.fpt_api_version() == 1
+    assert _lib.fpt_api_version() == 2
 
 
 def test_plan_accepts_workloads_without_gpu(lib):
@@ -126,7 +126,7 @@ def test_null_arguments(lib):
     assert lib.fpt_plan_workspace(None, None) == _lib.FPT_E_INVAL
     assert lib.fpt_simulate(None, None, None, None, None) == _lib.FPT_E_INVAL
     assert lib.fpt_histogram_all(None, None, None) == _lib.FPT_E_INVAL
-    assert lib.fpt_server_create(None, 0, 0, 0, None, None,
+    assert lib.fpt_server_create(None, 0, 0, 0, 0, None, None,
                                  ctypes.byref(ctypes.c_void_p())) == _lib.FPT_E_INVAL
     assert lib.fpt_submit(None, None, None) == _lib.FPT_E_INVAL
     assert lib.fpt_poll(None, 1, None, None, None) == _lib.FPT_E_INVAL
@@ -197,3 +197,13 @@ def test_default_start_needs_a_well(lib, model, gamma0, V0, ok):
             _lib.fpt_plan([p], "fp64")
         assert e.value.status == _lib.FPT_E_INVAL
         assert "default phi0" in e.value.message
+
+
+@pytest.mark.parametrize("model,scheme", [(0, 2), (1, 1), (2, 0)])
+def test_server_rejects_unknown_model_or_scheme(lib, model, scheme):
+    # validated before the pool is touched (any aligned address will do)
+    out = ctypes.c_void_p()
+    st = lib.fpt_server_create(ctypes.c_void_p(256), 1 << 30, _lib.FPT_FP32C, model, scheme,
+                               None, None, ctypes.byref(out))
+    assert st == _lib.FPT_E_INVAL
+    assert "model" in _lib.last_error() or "scheme" in _lib.last_error()

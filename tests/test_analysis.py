@@ -45,3 +45,28 @@ def test_fulton_dunkleberger_cdf_limits():
     # slower ramps switch earlier
     slow = analysis.fulton_dunkleberger_cdf(g, 0.283, 0.0673, 1e-8)
     assert np.all(slow >= P - 1e-12)
+
+
+@pytest.mark.parametrize("power", [0, -1])
+def test_barrier_fits_recover_the_exponent(power):
+    # tau = A T^power exp(dU / T): the Arrhenius slope (ln tau vs 1/T) is dU
+    # for power 0, the prefactor form (ln(T tau) vs 1/T) is dU for power -1
+    du, A = 0.0342, 37.0
+    T = du / np.array([3.5, 4.5, 5.5, 6.5])
+    tau = A * T ** power * np.exp(du / T)
+    se = 0.014 * tau
+    fits = analysis.barrier_fits(T, tau, se)
+    exact = "delta_U_arrhenius" if power == 0 else "delta_U_kramers_form"
+    assert fits[exact] == pytest.approx(du, rel=1e-12)
+    # the other form differs by the slope of ln T against 1/T
+    other = "delta_U_kramers_form" if power == 0 else "delta_U_arrhenius"
+    ln_t_slope = np.polyfit(1.0 / T, np.log(T), 1)[0]
+    assert fits[other] - fits[exact] == pytest.approx(ln_t_slope if power == 0 else -ln_t_slope,
+                                                      rel=1e-9)
+    # standard error of a weighted slope against numpy's covariance
+    rng = np.random.Generator(np.random.PCG64(3))
+    noisy = tau * np.exp(rng.normal(0, 0.014, size=4))
+    f2 = analysis.barrier_fits(T, noisy, 0.014 * noisy)
+    coef, cov = np.polyfit(1.0 / T, np.log(noisy), 1, w=1.0 / np.full(4, 0.014), cov="unscaled")
+    assert f2["delta_U_arrhenius"] == pytest.approx(coef[0], rel=1e-9)
+    assert f2["delta_U_arrhenius_se"] == pytest.approx(math.sqrt(cov[0, 0]), rel=1e-9)

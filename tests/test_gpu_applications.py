@@ -1,29 +1,114 @@
-"""The paper's physics checks run through the library (GPU): the barrier
-height recovered from an Arrhenius sweep (Sect. IV.A), and the switching
-distribution of a slow ramp against the adiabatic Fulton-Dunkleberger theory
-(Sect. IV.B).  Both compare with closed-form physics, not with the oracle."""
+"""The paper's physics checks run through the library (GPU): mean first-passage
+times over temperatures and the barrier recovered from them (Sect. IV.A,
+Eqs. (13)-(15), the Arrhenius-plot figure), and the switching distribution of
+a slow ramp against the adiabatic Fulton-Dunkleberger theory (Sect. IV.B).
+Each is also tied to the oracle at the same parameters, so a failure tells
+the physics reading apart from the implementation."""
+
+import math
 
 import numpy as np
 import pytest
+from scipy import stats
 
-from paper_1802_05065_amd import analysis
+import oracle
+from paper_1802_05065_amd import analysis, api, workloads
 
 pytestmark = pytest.mark.gpu
 
 
+def _op(p):
+    return oracle.OracleParams(**workloads.to_oracle_kwargs(p))
+
+
+def _oracle_at(p, first, n):
+    import concurrent.futures
+    import os
+
+    op = _op(p)
+    chunks = [(a, min(8, first + n - a)) for a in range(first, first + n, 8)]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        parts = list(ex.map(lambda c: oracle.escape_steps(op, c[0], c[1]), chunks))
+    return np.concatenate(parts)
+
+
 @pytest.mark.parametrize("precision", ["fp32c", "fp64"])
 def test_arrhenius_barrier(precision):
-    g, alpha = 0.5, 0.5
+    # gamma 0.5, damping 0.5 (moderate: the Kramers prefactor does not depend
+    # on T), Delta U / T = 4..7, 4096 replicas per temperature, escape to the
+    # next well.  Against the oracle: at every temperature the mean first
+    # passage time of 512 oracle replicas (independent seeds) lies within 3
+    # combined standard errors of the GPU's (1.1% family-wise over 4
+    # temperatures); FP64 also gives the oracle's steps replica by replica.
+    # Against the physics: the Arrhenius slope (Eq. (13)) and the
+    # quasipotential slope (Eqs. (14)-(15): ln(T tau) against 1/T) each lie
+    # within 5% of the same fits of the Kramers times at these temperatures,
+    # which is dU exactly for the Arrhenius form.  The 5% covers the
+    # explicit scheme's heating of the well at dt 0.02 (1.7% in the
+    # stationary temperature of its linearization, scheme_temperature), the
+    # O((T / dU)^2) correction to the slope and 3 standard errors of the
+    # fitted slope (0.7% of dU each).
+    g, alpha, dt = 0.5, 0.5, 0.02
     du = float(analysis.barrier_height(g))
     temps = [du / r for r in (4.0, 5.0, 6.0, 7.0)]
-    out = analysis.arrhenius_sweep(g, alpha, temps, n_replicas=4096, dt=0.02,
-                                   precision=precision)
-    print(out["delta_U"], out["delta_U_arrhenius"], out["delta_U_kramers_form"],
-          out["mean_fpt"], out["kramers_tau"])
+    out = analysis.arrhenius_sweep(g, alpha, temps, n_replicas=4096, dt=dt,
+                                   precision=precision, record_steps=True)
+    print(f"{precision}: dU {du:.4f}; Arrhenius fit {out['delta_U_arrhenius']:.4f} "
+          f"(+- {out['delta_U_arrhenius_se']:.4f}), quasipotential fit "
+          f"{out['delta_U_kramers_form']:.4f} vs theory {out['theory_delta_U_kramers_form']:.4f};"
+          f" tau {np.round(out['mean_fpt'], 1).tolist()} Kramers "
+          f"{np.round(out['kramers_tau'], 1).tolist()}")
     assert sum(out["censored"]) == 0
-    assert out["delta_U_arrhenius"] == pytest.approx(du, rel=0.08)
-    for tau, kt in zip(out["mean_fpt"], out["kramers_tau"]):
-        assert tau == pytest.approx(kt, rel=0.25)
+    assert out["theory_delta_U_arrhenius"] == pytest.approx(du, rel=1e-9)
+    assert out["delta_U_arrhenius"] == pytest.approx(du, rel=0.05)
+    assert out["delta_U_kramers_form"] == pytest.approx(out["theory_delta_U_kramers_form"],
+                                                        rel=0.05)
+    for i, s in enumerate(out["sets"]):
+        ref = _oracle_at(dict(s, seed=s["seed"] + 10_000), 0, 512) * dt
+        gpu_t = out["mean_fpt"][i]
+        se = math.sqrt(out["se"][i] ** 2 + ref.var() / ref.size)
+        print(f"  T {s['T']:.4f}: gpu {gpu_t:.1f} oracle {ref.mean():.1f} (3 SE {3 * se:.1f})")
+        assert abs(gpu_t - ref.mean()) < 3 * se, i
+    if precision == "fp64":
+        s = out["sets"][0]
+        ref = _oracle_at(s, 0, 128)
+        same = float(np.mean(out["steps"][0][:128] == ref))
+        print(f"  identical FP64 escape steps at T {s['T']:.4f}: {same:.4f}")
+        assert same >= 0.99
+
+
+def test_arrhenius_figure_reading():
+    # The Arrhenius-plot figure of Sect. IV.A: gamma 0.5, the printed 0.05
+    # as the potential amplitude V0 (its Delta U = 0.0342 = 0.05 dU(0.5)) and
+    # read literally as the damping too, h 0.004, 5120 realizations per
+    # temperature, Algorithm 1's own criterion (at rest in the well, escape
+    # past the barrier top).  The temperatures are not printed; Delta U / T =
+    # 3.5..6.5 spans the decade of mean times such a plot shows.  The paper
+    # reports 0.0303 (Arrhenius fit) and 0.0359 (prefactor fit) against
+    # 0.0342.  Bars: the Arrhenius slope within 10% of 0.0342 (the paper's
+    # own fit is 11% off), the prefactor-form slope within 10% of the same fit
+    # of the Kramers times, and the hottest temperature's FP64 escape steps
+    # identical to the oracle's for at least 99% of 128 replicas.
+    g, V0, alpha, dt = 0.5, 0.05, 0.05, 0.004
+    du = float(analysis.barrier_height(g, V0))
+    assert du == pytest.approx(0.0342, abs=5e-5)
+    temps = [du / r for r in (3.5, 4.5, 5.5, 6.5)]
+    out = analysis.arrhenius_sweep(g, alpha, temps, n_replicas=5120, dt=dt, V0=V0,
+                                   threshold="barrier", seed=700)
+    print(f"figure reading: dU {du:.4f}; Arrhenius fit {out['delta_U_arrhenius']:.4f} "
+          f"(paper 0.0303), prefactor fit {out['delta_U_kramers_form']:.4f} (paper 0.0359), "
+          f"theory fits {out['theory_delta_U_arrhenius']:.4f} / "
+          f"{out['theory_delta_U_kramers_form']:.4f}; tau {np.round(out['mean_fpt'], 0).tolist()}")
+    assert sum(out["censored"]) == 0
+    assert out["delta_U_arrhenius"] == pytest.approx(du, rel=0.10)
+    assert out["delta_U_kramers_form"] == pytest.approx(out["theory_delta_U_kramers_form"],
+                                                        rel=0.10)
+    hot = dict(out["sets"][0], n_replicas=128)
+    gpu = api.simulate(hot, "fp64").steps[0].cpu().numpy()
+    ref = _oracle_at(hot, 0, 128)
+    same = float(np.mean(gpu == ref))
+    print(f"  identical FP64 escape steps at the hottest temperature: {same:.4f}")
+    assert same >= 0.99
 
 
 def _fd_mean(alpha, T, ramp, **kw):
@@ -35,8 +120,11 @@ def _fd_mean(alpha, T, ramp, **kw):
 @pytest.mark.parametrize("scheme", [1, 0])
 def test_switching_cdf_matches_adiabatic_theory(scheme):
     # Li07 damping and temperature.  The semi-implicit scheme (1) samples the
-    # well at T (to 1e-4 at dt = 0.02) and is held to the theory.  The
-    # explicit scheme (0) heats the well bottom to 1.064 T, less at the higher
+    # well at T (to 1e-4 at dt = 0.02) and is held to the theory: the paper
+    # finds its distribution within 1.5% of the adiabatic one, and the
+    # largest deviation of an empirical CDF of 30000 draws from its own law
+    # is 0.005 at the median (Kolmogorov), so the bar is 0.02.  The explicit
+    # scheme (0) heats the well bottom to 1.064 T, less at the higher
     # energies escape passes through: its mean switching bias lies between
     # the theory at 1.064 T and the theory at T.
     a, T, ramp, dt = 0.283, 0.0673, 1e-6, 0.02
@@ -50,6 +138,29 @@ def test_switching_cdf_matches_adiabatic_theory(scheme):
     assert out["gamma_sw"].size == 30000
     se = float(np.std(out["gamma_sw"])) / np.sqrt(30000)
     if scheme == 1:
-        assert out["max_abs_diff"] < 0.05
+        assert out["max_abs_diff"] < 0.02
     else:
         assert m_hot + 3 * se < m < m_t - 3 * se
+
+
+def test_switching_cdf_parameters_fp64_match_oracle():
+    # the same ramp (Li07 damping and temperature, semi-implicit, dt 0.02) in
+    # the FP64 kernel: 96 replicas' switching steps against the oracle's
+    # (at least 99% identical), and a KS check of the FP32C run's first
+    # replicas' law against the oracle's
+    a, T, ramp, dt = 0.283, 0.0673, 1e-6, 0.02
+    per_step = ramp * dt
+    p = workloads.base_params(
+        model=workloads.UNDERDAMPED, alpha=a, T=T, gamma0=0.0, ramp=ramp, dt=dt, phi0=0.0,
+        v0=0.0, threshold=2.0 * math.pi, max_steps=int(math.ceil(1.005 / per_step)), seed=200,
+        n_replicas=96, n_bins=1024, hist_k_max=int(math.ceil(1.0 / per_step)), scheme=1)
+    gpu = api.simulate(p, "fp64").steps[0].cpu().numpy()
+    ref = _oracle_at(p, 0, 96)
+    same = float(np.mean(gpu == ref))
+    print(f"Li07 ramp, FP64: identical switching steps {same:.4f}; mean gamma_sw "
+          f"{(gpu * per_step).mean():.4f}")
+    assert (gpu > 0).all()
+    assert same >= 0.99
+    g32 = api.simulate(dict(p, n_replicas=4096, seed=201), "fp32c").steps[0].cpu().numpy()
+    ks = stats.ks_2samp(g32, ref)
+    assert ks.pvalue > 0.01

@@ -494,21 +494,22 @@ def test_batched_sets_equal_each_set_alone():
         assert np.mean(_steps(batch, i)[:8] == ref) >= 0.99
 
 
-@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
-def test_serving_alone_equals_mix(prec):
+@pytest.mark.parametrize("prec,scheme", [("fp32c", 0), ("fp64", 0), ("fp32c", 1)])
+def test_serving_alone_equals_mix(prec, scheme):
     import time
 
     import torch
 
     from paper_1802_05065_amd import _lib
 
-    jobs = workloads.batched_sets(n_sets=5, seed=9, log2_min=7, log2_max=10, ramp_scale=300.0)
+    jobs = [dict(j, scheme=scheme) for j in
+            workloads.batched_sets(n_sets=5, seed=9, log2_min=7, log2_max=10, ramp_scale=300.0)]
     pool = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     base = pool.data_ptr() + ((-pool.data_ptr()) % 256)
     stream = torch.cuda.current_stream()
     srv = _lib.fpt_server_create(base, (256 << 20) - 256, prec, 0,
                                  dict(waves_per_simd=2, steps_per_launch=1024),
-                                 stream.cuda_stream)
+                                 stream.cuda_stream, scheme=scheme)
     try:
         # three jobs, then (after the loop has drained its queue and packed
         # the running replicas into fewer lanes) two more that widen it again
@@ -535,6 +536,10 @@ def test_serving_alone_equals_mix(prec):
               f"{st['n_regroups']} regroups")
         assert st["finished"] == len(jobs)
         assert st["n_compactions"] >= 1
+        # every launch runs one integrator: a job of the other scheme is refused
+        with pytest.raises(_lib.FptError) as e:
+            _lib.fpt_submit(srv, dict(jobs[0], scheme=1 - scheme))
+        assert e.value.status == _lib.FPT_E_INVAL
     finally:
         _lib.fpt_server_destroy(srv)
     for i, j in enumerate(jobs):
@@ -564,6 +569,74 @@ def test_api_server_jobs_equal_plans():
         for k in INT_MOMENTS:
             assert mom[k] == alone.moments[0][k], k
         assert lat > 0
+
+
+def test_serving_admits_by_pool_memory():
+    # The smallest pool the server accepts holds the lane state, a work ring
+    # of 4096 chunks (2^18 replicas) and 4096 histogram bins.  Six jobs of
+    # 2^17 replicas with 2048 bins each: two fit the histogram region, so the
+    # others wait (queued) until a running job finishes and frees its bins;
+    # every job still finishes with the result it has alone.  A job whose
+    # replicas exceed the ring can never be admitted: FPT_E_NOMEM at submit.
+    import time
+
+    import torch
+
+    from paper_1802_05065_amd import _lib
+
+    tun = dict(waves_per_simd=2, steps_per_launch=2048)
+    stream = torch.cuda.current_stream()
+    pool = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    base = pool.data_ptr() + ((-pool.data_ptr()) % 256)
+
+    def fits(nbytes):
+        try:
+            _lib.fpt_server_destroy(_lib.fpt_server_create(base, nbytes, "fp32c", 0, tun,
+                                                           stream.cuda_stream))
+            return True
+        except _lib.FptError as e:
+            assert e.status == _lib.FPT_E_NOMEM
+            return False
+
+    lo, hi = 0, (256 << 20) - 256  # smallest accepted size, in 256-byte units
+    assert fits(hi) and not fits(lo)
+    while hi - lo > 256:
+        mid = (lo + hi) // 512 * 256
+        lo, hi = (lo, mid) if fits(mid) else (mid, hi)
+    print(f"smallest pool: {hi} bytes")
+    jobs = [dict(j, n_replicas=2 ** 17, n_bins=2048, hist_k_max=j["hist_k_max"])
+            for j in workloads.batched_sets(n_sets=6, seed=19, ramp_scale=300.0)]
+    srv = _lib.fpt_server_create(base, hi, "fp32c", 0, tun, stream.cuda_stream)
+    results, max_running, saw_queued = {}, 0, False
+    try:
+        with pytest.raises(_lib.FptError) as e:
+            _lib.fpt_submit(srv, dict(jobs[0], n_replicas=2 ** 18 + 1))
+        assert e.value.status == _lib.FPT_E_NOMEM
+        ids = {i: _lib.fpt_submit(srv, j) for i, j in enumerate(jobs)}
+        t0 = time.time()
+        while len(results) < len(jobs) and time.time() - t0 < 120:
+            st = _lib.fpt_server_stats_get(srv)
+            max_running = max(max_running, st["running"])
+            saw_queued |= st["queued"] > 0
+            for i, jid in ids.items():
+                if i not in results:
+                    r = _lib.fpt_poll(srv, jid, jobs[i]["n_bins"])
+                    if r is not None:
+                        results[i] = r
+            time.sleep(0.002)
+        st = _lib.fpt_server_stats_get(srv)
+    finally:
+        _lib.fpt_server_destroy(srv)
+    print(f"finished {len(results)} of {len(jobs)}, at most {max_running} running, "
+          f"queued seen {saw_queued}, {st['n_launches']} launches")
+    assert len(results) == len(jobs)
+    assert saw_queued and max_running <= 2
+    for i, j in enumerate(jobs):
+        alone = api.simulate(j, "fp32c", FIXED, record_steps=False)
+        counts, mom, _ = results[i]
+        assert counts.tolist() == alone.counts[0].tolist(), i
+        for k in INT_MOMENTS:
+            assert mom[k] == alone.moments[0][k], (i, k)
 
 
 # ---------------------------------------------------------------------------
@@ -711,7 +784,9 @@ def test_batched_fp32c_statistics_per_set():
         print(f"set {i} alpha {alpha} T {T} ramp {ramp}: KS p {ks.pvalue:.3f}, mean "
               f"{ea.mean():.1f} vs {eb.mean():.1f} ({(ea.mean() - eb.mean()) / se:+.2f} SE), "
               f"censored {ca:.4f} vs {cb:.4f}")
-        assert ea.size > n // 2 and eb.size > n // 2, i
+        # (a strongly damped, cold set may mostly run past the cap: its
+        # censored fraction is the comparison then, with the escaped rest)
+        assert min(ea.size, eb.size) >= 256, i
         assert ks.pvalue > 0.01 / len(BATCHED_KS_SETS), i
         assert abs(ea.mean() - eb.mean()) < 3 * se, i
         assert abs(ca - cb) < 3 * se_c, i
