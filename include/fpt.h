@@ -213,6 +213,29 @@ fpt_status fpt_simulate(fpt_plan_t plan, void* workspace,
                         int64_t* const* out_steps, uint64_t* out_hist,
                         void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): fpt_simulate with
+ * the workspace in a static device array of the library, of
+ * FPT_NOALLOC_SCRATCH_BYTES, which each GPU the library runs on holds from
+ * its first use until the process ends.  The call allocates nothing: no
+ * device or pinned memory, no events, no graphs; the caller still passes the
+ * outputs (as for fpt_simulate; out_hist NULL keeps the histograms in the
+ * static array until the next call on that GPU).
+ *   - the plan's tuning must be complete (replicas_per_lane, waves_per_simd,
+ *     steps_per_launch non-zero; no autotuning trials) with use_graph 0,
+ *     else FPT_E_INVAL;
+ *   - the workspace of the plan at that launch shape (laid out for the shape
+ *     itself, not for the largest one fpt_plan_workspace reports) must fit
+ *     the array, else FPT_E_NOMEM;
+ *   - every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents (each call clears what it needs at zero): calls that
+ *     overlap on one GPU, from several threads or streams, race;
+ *   - results equal fpt_simulate's for the same plan; fpt_histogram(_all)
+ *     and fpt_plan_stats read this run (kernel_ms stays 0: no events). */
+#define FPT_NOALLOC_SCRATCH_BYTES (48ull << 20)
+fpt_status fpt_simulate_noalloc(fpt_plan_t plan, int64_t* const* out_steps,
+                                uint64_t* out_hist, void* stream);
+
 /* Copy set `set`'s histogram (n_bins counts) and moments of the last
  * fpt_simulate to host memory: the escape-time histogram of Sect. II.B and
  * the switching-current histogram / CDF of Sect. IV.B (bins over escape

@@ -137,6 +137,7 @@ SIGNATURES = [
                                 ctypes.POINTER(FptTuning), ctypes.POINTER(_VP)]),
     ("fpt_plan_workspace", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
     ("fpt_simulate", ctypes.c_int, [_VP, _VP, ctypes.POINTER(_VP), _VP, _VP]),
+    ("fpt_simulate_noalloc", ctypes.c_int, [_VP, ctypes.POINTER(_VP), _VP, _VP]),
     ("fpt_histogram", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
                                      ctypes.POINTER(FptMoments)]),
     ("fpt_histogram_all", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint64),
@@ -244,6 +245,17 @@ def fpt_simulate(plan: int, workspace: int, out_steps: Optional[Sequence[int]],
     if out_steps is not None:
         steps_arr = (ctypes.c_void_p * len(out_steps))(*[p or None for p in out_steps])
     check(lib().fpt_simulate(plan, workspace, steps_arr, out_hist or None, stream or None))
+
+
+def fpt_simulate_noalloc(plan: int, out_steps: Optional[Sequence[int]],
+                         out_hist: Optional[int], stream: Optional[int]) -> None:
+    steps_arr = None
+    if out_steps is not None:
+        steps_arr = (ctypes.c_void_p * len(out_steps))(*[p or None for p in out_steps])
+    check(lib().fpt_simulate_noalloc(plan, steps_arr, out_hist or None, stream or None))
+
+
+NOALLOC_SCRATCH_BYTES = 48 << 20  # FPT_NOALLOC_SCRATCH_BYTES of include/fpt.h
 
 
 def fpt_histogram(plan: int, set_index: int, n_bins: int):

@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfpt.so")
 ISA_RATES = os.path.join(HERE, "isa_rates")
 
-SOURCES = ["kernels.hip", "runtime.cpp", "autotune.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "autotune.cpp", "server.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FPT_OFFLOAD_ARCH", "gfx950")

@@ -14,7 +14,21 @@ namespace fpt {
 // Launches near the end of a refill run are this many times shorter.
 constexpr int32_t kTailLaunchDivisor = 8;
 
-struct Plan {
+// Workspace layout: byte offsets of the regions for `max_slots` lane-state
+// slots.
+struct WsLayout {
+  uint64_t max_slots = 0;
+  uint64_t off_sets = 0, off_chunks = 0, off_ctr = 0, off_mom = 0, off_hist = 0;
+  uint64_t off_st_phi = 0, off_st_v = 0, off_st_j = 0, off_st_idx = 0, off_st_set = 0;
+  uint64_t off_st_mt = 0;
+  // second lane-state buffer for tail compaction (refill plans without MT)
+  uint64_t off_alt_phi = 0, off_alt_v = 0, off_alt_j = 0, off_alt_idx = 0, off_alt_set = 0;
+  bool has_alt = false;
+  uint64_t off_group = 0;       // per-set positions of a regrouping (multi-set)
+  uint64_t ws_bytes = 0;
+};
+
+struct Plan : WsLayout {
   std::vector<fpt_params> params;
   std::vector<SetDev> sets;     // derived constants, hist offsets
   std::vector<Chunk> chunks;    // multi-set work queue (64 replicas per entry)
@@ -30,16 +44,8 @@ struct Plan {
   int cus = 256;
   std::string arch = "gfx950";
 
-  // workspace layout (byte offsets)
-  uint64_t max_slots = 0;
-  uint64_t off_sets = 0, off_chunks = 0, off_ctr = 0, off_mom = 0, off_hist = 0;
-  uint64_t off_st_phi = 0, off_st_v = 0, off_st_j = 0, off_st_idx = 0, off_st_set = 0;
-  uint64_t off_st_mt = 0;
-  // second lane-state buffer for tail compaction (refill plans without MT)
-  uint64_t off_alt_phi = 0, off_alt_v = 0, off_alt_j = 0, off_alt_idx = 0, off_alt_set = 0;
-  bool has_alt = false;
-  uint64_t off_group = 0;       // per-set positions of a regrouping (multi-set)
-  uint64_t ws_bytes = 0;
+  // the workspace layout (WsLayout) is sized for the largest launch shape;
+  // a run in the library's static scratch lays it out for its own shape
 
   // last run
   uint64_t n_lanes = 0;
@@ -50,13 +56,18 @@ struct Plan {
   fpt_run_stats stats{};
 
   // host resources (created lazily, on the first simulate)
-  Counters* h_ctr = nullptr;    // pinned
+  Counters* h_ctr = nullptr;    // pinned (a run in the static scratch points it
+                                // at h_ctr_plain instead)
+  Counters h_ctr_plain{};
+  std::vector<SetDev> upload;   // set table as uploaded (sized with the plan)
+  bool noalloc = false;         // the current run allocates nothing
   std::vector<hipEvent_t> events;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;  // capture / replay stream of the graph path
 
   ~Plan();
-  fpt_status layout();
+  // lay out the workspace for `slots` lane-state slots (0: the largest shape)
+  fpt_status layout(uint64_t slots = 0);
   SliceArgs slice_args(char* ws, uint64_t* hist, uint64_t n_lanes, int buf = 0) const;
   fpt_status maybe_compact(char* ws, SliceArgs& a, int& buf, uint64_t& lanes, int R,
                            hipStream_t st, bool* compacted);
@@ -80,6 +91,11 @@ struct Plan {
   fpt_status resolve_tuning(char* ws, hipStream_t st);
   fpt_status simulate(void* workspace, int64_t* const* out_steps, uint64_t* out_hist,
                       hipStream_t st);
+  // fpt_simulate in caller-independent scratch memory: `scratch` of
+  // `scratch_bytes` (the library's static device array); no allocation
+  fpt_status simulate_in_scratch(void* scratch, uint64_t scratch_bytes,
+                                 int64_t* const* out_steps, uint64_t* out_hist,
+                                 hipStream_t st);
   fpt_status histogram(int32_t set, uint64_t* host_counts, fpt_moments* host_m);
   fpt_status histogram_all(uint64_t* host_counts, fpt_moments* host_m);
   fpt_status run_stats(fpt_run_stats* out);
@@ -91,3 +107,8 @@ fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision
 const char* last_error();
 
 }  // namespace fpt
+
+// The C ABI's opaque plan handle.
+struct fpt_plan_s {
+  fpt::Plan* impl;
+};

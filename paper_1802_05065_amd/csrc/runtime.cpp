@@ -184,16 +184,17 @@ static bool verbose() {
 
 static uint64_t align256(uint64_t x) { return round_up(x, 256); }
 
-fpt_status Plan::layout() {
-  const DeviceInfo di = device_info();
-  cus = di.cus;
-  arch = di.arch;
-  uint64_t slots;
-  const uint64_t max_r = mt ? 1 : kMaxReplicasPerLane;
-  if (tuning_req.schedule == FPT_SCHED_ONE_PER_LANE) {
-    slots = round_up(std::max<uint64_t>(total_flat, 1), kBlockThreads * max_r);
-  } else {
-    slots = (uint64_t)cus * 4 * kMaxWavesPerSimd * kWave * max_r;
+fpt_status Plan::layout(uint64_t slots) {
+  if (slots == 0) {
+    const DeviceInfo di = device_info();
+    cus = di.cus;
+    arch = di.arch;
+    const uint64_t max_r = mt ? 1 : kMaxReplicasPerLane;
+    if (tuning_req.schedule == FPT_SCHED_ONE_PER_LANE) {
+      slots = round_up(std::max<uint64_t>(total_flat, 1), kBlockThreads * max_r);
+    } else {
+      slots = (uint64_t)cus * 4 * kMaxWavesPerSimd * kWave * max_r;
+    }
   }
   max_slots = slots;
   uint64_t off = 0;
@@ -451,7 +452,7 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
   ran = false;
   stream = st;
 
-  FPT_TRY(resolve_tuning(ws, st));
+  if (!noalloc) FPT_TRY(resolve_tuning(ws, st));  // the scratch run set `tuning` itself
   const int R = tuning.replicas_per_lane;
   const bool refill = tuning.schedule == FPT_SCHED_REFILL;
   n_lanes = lanes_for(tuning);
@@ -461,10 +462,12 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
                 (unsigned long long)n_slots, (unsigned long long)max_slots);
   const int blocks = tuning.steps_per_launch / 4;
 
-  std::vector<SetDev> table = sets;
-  for (size_t i = 0; i < table.size(); ++i)
-    table[i].out_steps = out_steps ? out_steps[i] : nullptr;
-  FPT_TRY(upload_sets(ws, table, st));
+  // the uploaded table (sized with the plan) carries this call's outputs
+  for (size_t i = 0; i < sets.size(); ++i) {
+    upload[i] = sets[i];
+    upload[i].out_steps = out_steps ? out_steps[i] : nullptr;
+  }
+  FPT_TRY(upload_sets(ws, upload, st));
 
   // multi-set refill runs keep wavefronts to one set (enqueue_regroup)
   const bool regroup = regroups(tuning);
@@ -567,16 +570,23 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
     FPT_HIP(hipEventRecord(events[3], graph_stream));
     FPT_HIP(hipStreamWaitEvent(st, events[3], 0));
   } else {
+    // a run in the static scratch creates no events: it waits on the stream
+    // and leaves kernel_ms at 0
+    if (!noalloc) marks.reserve(16);
     while (!finished) {
-      FPT_TRY(ensure_host_resources(ev_used + 2 * group + 1));
+      if (!noalloc) FPT_TRY(ensure_host_resources(ev_used + 2 * group + 1));
       const uint32_t groups = (uint32_t)(lanes / kBlockThreads);
       const bool regroup_now = regroup && last_cursor < total_flat;
       for (int i = 0; i < group; ++i) {
-        hipEvent_t e0 = events[ev_used++], e1 = events[ev_used++];
-        FPT_HIP(hipEventRecord(e0, st));
-        FPT_HIP(launch_slice(fp64, model, R, multi, a, groups, st));
-        FPT_HIP(hipEventRecord(e1, st));
-        marks.emplace_back(e0, e1);
+        if (noalloc) {
+          FPT_HIP(launch_slice(fp64, model, R, multi, a, groups, st));
+        } else {
+          hipEvent_t e0 = events[ev_used++], e1 = events[ev_used++];
+          FPT_HIP(hipEventRecord(e0, st));
+          FPT_HIP(launch_slice(fp64, model, R, multi, a, groups, st));
+          FPT_HIP(hipEventRecord(e1, st));
+          marks.emplace_back(e0, e1);
+        }
         if (regroup_now) {
           FPT_TRY(enqueue_regroup(ws, a, buf, lanes, R, st));
           ++stats.n_regroups;
@@ -585,9 +595,13 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
         blocks_issued += (uint64_t)a.blocks;
       }
       FPT_HIP(hipMemcpyAsync(h_ctr, a.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
-      hipEvent_t sync = events[ev_used++];
-      FPT_HIP(hipEventRecord(sync, st));
-      FPT_HIP(hipEventSynchronize(sync));
+      if (noalloc) {
+        FPT_HIP(hipStreamSynchronize(st));
+      } else {
+        hipEvent_t sync = events[ev_used++];
+        FPT_HIP(hipEventRecord(sync, st));
+        FPT_HIP(hipEventSynchronize(sync));
+      }
       for (auto& m : marks) {
         float ms = 0.f;
         FPT_HIP(hipEventElapsedTime(&ms, m.first, m.second));
@@ -615,7 +629,7 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
         group = 1;
     }
   }
-  if (total_replicas == 0) FPT_TRY(ensure_host_resources(1));
+  if (total_replicas == 0 && !noalloc) FPT_TRY(ensure_host_resources(1));
   if (total_replicas > 0) {
     stats.lane_steps = h_ctr->lane_steps;
     stats.extra_passes = h_ctr->extra_passes;
@@ -627,6 +641,45 @@ fpt_status Plan::simulate(void* workspace, int64_t* const* out_steps,
           .count();
   ran = true;
   return FPT_OK;
+}
+
+// fpt_simulate without any allocation: the workspace is `scratch` (the
+// library's static device array of `scratch_bytes`), laid out for this
+// call's own launch shape instead of the largest one.  The tuning must be
+// complete (no autotuning trials) and graph-free; the counters come back
+// through plan-owned host memory and no events are created.
+fpt_status Plan::simulate_in_scratch(void* scratch, uint64_t scratch_bytes,
+                                     int64_t* const* out_steps, uint64_t* out_hist,
+                                     hipStream_t st) {
+  const fpt_tuning& t = tuning_req;
+  if (t.replicas_per_lane == 0 || t.waves_per_simd == 0 || t.steps_per_launch == 0)
+    return fail(FPT_E_INVAL,
+                "the allocation-free run needs a complete tuning (replicas_per_lane, "
+                "waves_per_simd, steps_per_launch): it runs no autotuning trials");
+  if (t.use_graph)
+    return fail(FPT_E_INVAL, "the allocation-free run does not replay graphs (use_graph 0)");
+  fpt_tuning used = t;
+  used.waves_per_simd = std::min(used.waves_per_simd, resident_waves(used.replicas_per_lane));
+  const uint64_t slots = lanes_for(used) * (uint64_t)used.replicas_per_lane;
+  const WsLayout full = *this;
+  FPT_TRY(layout(slots));
+  if (ws_bytes > scratch_bytes) {
+    const uint64_t need = ws_bytes;
+    static_cast<WsLayout&>(*this) = full;
+    return fail(FPT_E_NOMEM,
+                "the plan needs %llu bytes of workspace at its launch shape; the library's "
+                "static scratch holds %llu (use fpt_simulate with a workspace)",
+                (unsigned long long)need, (unsigned long long)scratch_bytes);
+  }
+  Counters* pinned = h_ctr;
+  h_ctr = &h_ctr_plain;
+  noalloc = true;
+  tuning = used;
+  const fpt_status res = simulate(scratch, out_steps, out_hist, st);
+  noalloc = false;
+  h_ctr = pinned;
+  static_cast<WsLayout&>(*this) = full;
+  return res;
 }
 
 fpt_status Plan::histogram(int32_t set, uint64_t* host_counts, fpt_moments* host_m) {
@@ -764,6 +817,7 @@ fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision
     p->sets.push_back(s);
   }
   p->hist_bins = off;
+  p->upload = p->sets;
   if (p->multi) {
     // the work queue takes the sets longest-expected first, so the replicas
     // that set the end of the run start early (results do not depend on it)
@@ -800,10 +854,6 @@ fpt_status make_plan(const fpt_params* params, int32_t n_sets, int32_t precision
 // C ABI
 
 using fpt::Plan;
-
-struct fpt_plan_s {
-  Plan* impl;
-};
 
 extern "C" {
 

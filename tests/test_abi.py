@@ -128,6 +128,7 @@ def test_null_arguments(lib):
     assert lib.fpt_histogram_all(None, None, None) == _lib.FPT_E_INVAL
     assert lib.fpt_server_create(None, 0, 0, 0, 0, None, None,
                                  ctypes.byref(ctypes.c_void_p())) == _lib.FPT_E_INVAL
+    assert lib.fpt_simulate_noalloc(None, None, None, None) == _lib.FPT_E_INVAL
     assert lib.fpt_submit(None, None, None) == _lib.FPT_E_INVAL
     assert lib.fpt_poll(None, 1, None, None, None) == _lib.FPT_E_INVAL
     assert "NULL" in _lib.last_error()
