@@ -209,9 +209,10 @@ def _oracle_processes(tasks):
 def cpu_baseline(n_rep: int, procs: int):
     """The FP64 oracle on the host cores: the benchmark workload's first
     `n_rep` replicas split over `procs` processes (the line's value), and
-    per-workload rates: the plain fixed-bias workload in full (one process),
-    16384 replicas of the uneven overdamped workload and one replica of each
-    of the batched workload's first 16 sets (16 processes each)."""
+    per-workload rates: the plain fixed-bias workload in full (one process,
+    about 0.1 s), 32768 replicas of the uneven overdamped workload and one
+    replica of each of the batched workload's first 16 sets (16 processes
+    each)."""
     from paper_1802_05065_amd import workloads
 
     procs = max(1, min(procs, n_rep))
@@ -231,9 +232,9 @@ def cpu_baseline(n_rep: int, procs: int):
 
     record("plain_escape_full", [(workloads.plain_escape(), 0, 1024)],
            "fixed-bias workload, all 1024 replicas, one process")
-    p3 = workloads.uneven_overdamped(n_replicas=16384)
-    record("uneven_16384", [(p3, i * 1024, 1024) for i in range(16)],
-           "uneven overdamped workload, replicas 0..16383, 16 processes of 1024")
+    p3 = workloads.uneven_overdamped(n_replicas=32768)
+    record("uneven_32768", [(p3, i * 2048, 2048) for i in range(16)],
+           "uneven overdamped workload, replicas 0..32767, 16 processes of 2048")
     sets = workloads.batched_sets(n_sets=256, seed=4)
     record("batched_16_sets", [(s, 0, 1) for s in sets[:16]],
            "batched workload, replica 0 of sets 0..15, one process each")
