@@ -137,7 +137,8 @@ def parse():
     ap.add_argument("--serve-rho", type=float, default=0.7,
                     help="offered load of the rate-scaled trace, as a fraction of the "
                          "measured FP32C throughput")
-    ap.add_argument("--mode", choices=("switching", "uneven", "batched", "mt", "next", "serve"),
+    ap.add_argument("--mode", choices=("switching", "uneven", "batched", "mt", "next", "serve",
+                                       "identical"),
                     default="switching",
                     help="switching: the benchmark line (default); uneven: refill vs "
                          "one-replica-per-lane on the uneven overdamped workload; batched: "
@@ -145,10 +146,13 @@ def parse():
                          "the switching workload with per-replica MT19937 against Philox; "
                          "next: rates of the semi-implicit scheme and of the Arrhenius and "
                          "switching-distribution analyses; serve: the serving legs alone, "
-                         "with --serve-seconds / --literal-seconds as given")
+                         "with --serve-seconds / --literal-seconds as given; identical: the "
+                         "single-set against the multi-set kernel on identical sets")
     ap.add_argument("--capacity", type=float, default=1.43e12,
                     help="serve mode: the FP32C replica-steps/s the rate-scaled trace is "
                          "scaled to")
+    ap.add_argument("--waves", default="7,8",
+                    help="identical mode: waves per SIMD to run (comma separated)")
     ap.add_argument("--ramp-scale", type=float, default=1.0,
                     help="batched mode: multiply every ramp (shorter runs)")
     ap.add_argument("--no-regroup", action="store_true",
@@ -645,6 +649,36 @@ def serving_legs(args, capacity):
     return out
 
 
+def identical_mode(args):
+    """The same work as one set and as 16 identical sets: 2^22 replicas of a
+    1e-4 ramp (the benchmark workload's physics, 200000-step cap), FP32C,
+    R = 1, 16384-step launches, at each wave count of --waves.  One plan per
+    line, no untimed runs (the tuning is fixed), so a counter run sees only
+    these launches; kernel lane-steps/s compare the single-set and the
+    multi-set kernel issuing the same work."""
+    import torch
+
+    from paper_1802_05065_amd import api, workloads
+
+    base = workloads.switching_ramp(n_replicas=2 ** 22, seed=11) | dict(
+        ramp=1e-4, max_steps=201_000, hist_k_max=200_000)
+    for w in (int(x) for x in args.waves.split(",")):
+        tun = dict(replicas_per_lane=1, waves_per_simd=w, steps_per_launch=16384)
+        for n_sets in (1, 16):
+            sets = [dict(base, n_replicas=2 ** 22 // n_sets, seed=100 + i) for i in range(n_sets)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = api.simulate(sets, "fp32c", tun, record_steps=False)
+            t1 = time.perf_counter()
+            st = r.stats
+            print(json.dumps({
+                "waves_per_simd": w, "sets": n_sets, "lane_steps": st["lane_steps"],
+                "replica_steps": st["replica_steps"], "launches": st["n_launches"],
+                "kernel_lane_steps_per_s": st["lane_steps"] / (st["kernel_ms"] * 1e-3),
+                "replica_steps_per_s": st["replica_steps"] / (t1 - t0),
+                "lane_utilization": st["replica_steps"] / st["lane_steps"]}), flush=True)
+
+
 def serve_mode(args):
     """The serving legs alone, against the capacity the benchmark line
     measured (`--capacity`, default 1.43e12 replica-steps/s)."""
@@ -678,6 +712,9 @@ def main():
         return
     if args.mode == "serve":
         serve_mode(args)
+        return
+    if args.mode == "identical":
+        identical_mode(args)
         return
     import numpy as np
     import torch

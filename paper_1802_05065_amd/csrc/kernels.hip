@@ -563,21 +563,29 @@ __device__ __forceinline__ void finish_slot(LdsTables& tab, const SliceArgs& a,
                                             Slot<FP64>& sl, uint64_t& amask, uint32_t& safe,
                                             const uint64_t (&esc)[4], uint64_t lane_bit,
                                             uint32_t set_u) {
-  // set_u == kInactive: the set of the first active lane (all active lanes
-  // share it), found only where it is needed
-  if (!LANE_SET && set_u == kInactive)
-    set_u = amask ? (uint32_t)__builtin_amdgcn_readlane(
-                        (int)sl.set, __ffsll((unsigned long long)amask) - 1)
-                  : 0u;
-  const ConstSetDev& su = ((ConstSetDev*)a.sets)[set_u];
+  // The set's constants: set set_u, or for kInactive the set of the first
+  // active lane (all active lanes share it).  Looked up only on the paths
+  // that read them -- a step-cap check, a finished replica -- and always
+  // first while amask still holds the block's lanes; the common block (no
+  // finish, no cap check) does no lookup at all.
+  uint32_t su_idx = set_u;
+  auto su = [&]() -> const ConstSetDev& {
+    if (!LANE_SET && su_idx == kInactive)
+      su_idx = amask ? (uint32_t)__builtin_amdgcn_readlane(
+                           (int)sl.set, __ffsll((unsigned long long)amask) - 1)
+                     : 0u;
+    return ((const ConstSetDev*)a.sets)[su_idx];
+  };
   const uint64_t crossed = (esc[0] | esc[1] | esc[2] | esc[3]) & amask;
   const bool check_cap = safe == 0;
   uint64_t last = 0ull;
   if (check_cap) {
-    const uint64_t jm = LANE_SET ? slot_jmax<true>(a, sl, (amask & lane_bit) != 0, 0ull) : su.jmax;
+    const uint64_t jm = LANE_SET ? slot_jmax<true>(a, sl, (amask & lane_bit) != 0, 0ull)
+                                 : su().jmax;
     last = __ballot(sl.j >= jm) & amask;
   }
   if (crossed | last) {
+    const ConstSetDev* sp = LANE_SET ? nullptr : &su();
     bool fin = false;
     int64_t k = -1;
     if ((crossed | last) & lane_bit) {
@@ -587,11 +595,11 @@ __device__ __forceinline__ void finish_slot(LdsTables& tab, const SliceArgs& a,
       else if (esc[2] & lane_bit) q1 = 3;
       else if (esc[3] & lane_bit) q1 = 4;
       const int64_t kesc = q1 ? (int64_t)(4 * sl.j) + q1 : 0;
-      const int64_t max_steps = LANE_SET ? a.sets[sl.set].max_steps : su.max_steps;
+      const int64_t max_steps = LANE_SET ? a.sets[sl.set].max_steps : sp->max_steps;
       if (q1 && kesc <= max_steps) {
         fin = true;
         k = kesc;
-      } else if (sl.j >= (LANE_SET ? slot_jmax<true>(a, sl, true, 0ull) : su.jmax)) {
+      } else if (sl.j >= (LANE_SET ? slot_jmax<true>(a, sl, true, 0ull) : sp->jmax)) {
         fin = true;
         k = -1;
       }
@@ -604,7 +612,7 @@ __device__ __forceinline__ void finish_slot(LdsTables& tab, const SliceArgs& a,
   sl.kd += 4.0;
   if (check_cap) {
     const bool act = (amask & lane_bit) != 0;
-    safe = blocks_to_cap(sl, LANE_SET ? slot_jmax<true>(a, sl, act, 0ull) : su.jmax, act);
+    safe = blocks_to_cap(sl, LANE_SET ? slot_jmax<true>(a, sl, act, 0ull) : su().jmax, act);
   } else {
     --safe;
   }
@@ -720,6 +728,26 @@ __device__ __forceinline__ void slice_body(const SliceArgs& a) {
     for (int r = 0; r < R; ++r) any |= amask[r];
     if (any == 0) break;
     ++blocks_run;
+
+    if constexpr (!MULTI && R == 1 && !MT && !FP64) {
+      // Every lane busy: run blocks without the refill test until one of
+      // them finishes (its slot refills above in the next block) or the
+      // launch ends.  (FP32C only: in the FP64 kernel the second copy of
+      // the block costs more spilled scalar registers than the test.)
+      if (amask[0] == ~0ull) {
+        for (;;) {
+          uint64_t e1[1][4];
+          float ph_q[1][5];
+          block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, P, gA, ph_q);
+          threshold_f32(ph_q[0], s[0].e, P.p.th_near_rev, P.p.th_rev, amask[0], e1[0]);
+          finish_slot<false>(tab, a, s[0], amask[0], safe[0], e1[0], lane_bit, 0u);
+          if (amask[0] != ~0ull || blk + 1 >= a.blocks) break;
+          ++blk;
+          ++blocks_run;
+        }
+        continue;
+      }
+    }
 
     if constexpr (MULTI && R == 1) {
       // Wavefronts that refill only when free in every lane: while all active

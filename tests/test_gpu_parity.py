@@ -487,11 +487,11 @@ def test_batched_sets_equal_each_set_alone():
             assert batch.counts[i].tolist() == alone.counts[0].tolist()
             for k in INT_MOMENTS:
                 assert batch.moments[i][k] == alone.moments[0][k], (prec, i, k)
-    # FP64 batch against the oracle on sampled replicas
+    # FP64 batch (autotuned) against the oracle: 64 replicas of every set
     batch = api.simulate(sets, "fp64", None)
-    for i, s in enumerate(sets[:3]):
-        ref = oracle.escape_steps(_op(s), 0, 8)
-        assert np.mean(_steps(batch, i)[:8] == ref) >= 0.99
+    for i, s in enumerate(sets):
+        ref = _oracle_at(s, range(64))
+        assert np.mean(_steps(batch, i)[:64] == ref) >= 0.99, i
 
 
 @pytest.mark.parametrize("prec,scheme", [("fp32c", 0), ("fp64", 0), ("fp32c", 1)])
