@@ -22,6 +22,7 @@ from ._lib import (  # noqa: F401
     FptError,
     fpt_api_version,
     fpt_histogram,
+    fpt_histogram_all,
     fpt_last_error,
     fpt_mt_words,
     fpt_normals,
@@ -35,6 +36,7 @@ from ._lib import (  # noqa: F401
     fpt_server_destroy,
     fpt_server_stats_get,
     fpt_simulate,
+    fpt_simulate_noalloc,
     fpt_submit,
     fpt_trajectory,
 )
