@@ -231,7 +231,11 @@ fpt_status fpt_simulate(fpt_plan_t plan, void* workspace,
  *     call's contents (each call clears what it needs at zero): calls that
  *     overlap on one GPU, from several threads or streams, race;
  *   - results equal fpt_simulate's for the same plan; fpt_histogram(_all)
- *     and fpt_plan_stats read this run (kernel_ms stays 0: no events). */
+ *     and fpt_plan_stats read this run (kernel_ms stays 0: no events);
+ *   - like fpt_simulate, the call drives its launches from the host and
+ *     returns when the run has finished (it waits on `stream` between
+ *     launch groups), so it is not itself recorded into a stream capture:
+ *     what it spares its caller is every allocation and handle creation. */
 #define FPT_NOALLOC_SCRATCH_BYTES (48ull << 20)
 fpt_status fpt_simulate_noalloc(fpt_plan_t plan, int64_t* const* out_steps,
                                 uint64_t* out_hist, void* stream);
