@@ -349,7 +349,6 @@ def uneven_mode(args):
     import numpy as np
     import torch
 
-    import oracle.appendix_a as appendix_a
     from paper_1802_05065_amd import api, workloads
 
     p = workloads.uneven_overdamped(n_replicas=args.replicas if args.replicas != 2 ** 20
@@ -385,11 +384,20 @@ def uneven_mode(args):
     per_slot = p["n_replicas"] / (out["refill"]["tuning"]["waves_per_simd"] * 4 * 64 *
                                   torch.cuda.get_device_properties(0).multi_processor_count *
                                   out["refill"]["tuning"]["replicas_per_lane"])
+    # Appendix A's model: unit-exponential run times, so a thread with n_load
+    # runs takes an Erlang(n_load, 1) time and the wavefront the largest of
+    # its threads' times; efficiency = n_load / E[that maximum].  For one run
+    # per thread E[max] is the harmonic number H_lanes; for a fixed share it
+    # is estimated here by sampling.
+    harmonic = sum(1.0 / i for i in range(1, lanes + 1))
+    n_load = max(1, round(per_slot))
+    static_eff = n_load / rng.gamma(n_load, size=(20000, lanes)).max(axis=1).mean()
     out["appendix_a"] = {
         "threads": lanes,
-        "exponential_model_efficiency": appendix_a.efficiency(lanes, 1),
+        "exponential_model_efficiency": 1.0 / harmonic,
         "empirical_escape_law_efficiency": float(emp),
-        "static_partition_efficiency": appendix_a.efficiency(lanes, max(1, round(per_slot))),
+        "static_partition_efficiency": float(static_eff),
+        "static_partition_runs_per_thread": n_load,
         "static_partition_note": "Appendix A's model with each of the 64 threads of a "
                                  "wavefront given a fixed share of round(replicas per slot) "
                                  "jobs; refill assigns them dynamically instead",
