@@ -208,3 +208,30 @@ def test_server_rejects_unknown_model_or_scheme(lib, model, scheme):
                                None, None, ctypes.byref(out))
     assert st == _lib.FPT_E_INVAL
     assert "model" in _lib.last_error() or "scheme" in _lib.last_error()
+
+
+def test_header_is_pedantic_c99_and_cxx(tmp_path):
+    # include/fpt.h is the boundary for C callers too: it compiles as strict
+    # ISO C99 and as C++17 with every warning an error
+    import subprocess
+
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "use_fpt.c"
+    src.write_text('#include <string.h>\n'
+                   '#include "fpt.h"\n'
+                   "int main(void) {\n"
+                   "  fpt_params p;\n"
+                   "  fpt_tuning t;\n"
+                   "  fpt_moments m;\n"
+                   "  memset(&p, 0, sizeof p);\n"
+                   "  memset(&t, 0, sizeof t);\n"
+                   "  memset(&m, 0, sizeof m);\n"
+                   "  (void)p; (void)t; (void)m;\n"
+                   "  return FPT_API_VERSION == 2 && FPT_NOALLOC_SCRATCH_BYTES > 0 ? 0 : 1;\n"
+                   "}\n")
+    for cmd in (["gcc", "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror",
+                 "-fsyntax-only", "-I" + inc, str(src)],
+                ["g++", "-std=c++17", "-pedantic", "-Wall", "-Wextra", "-Werror",
+                 "-fsyntax-only", "-x", "c++", "-I" + inc, str(src)]):
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        assert res.returncode == 0, res.stderr
