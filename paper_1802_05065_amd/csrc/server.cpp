@@ -122,7 +122,6 @@ struct Server {
 
   Counters* h_ctr = nullptr;   // pinned
   MomDev* h_mom = nullptr;     // pinned, kMaxSets
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   std::mutex mu;
   std::condition_variable cv;
@@ -234,8 +233,6 @@ fpt_status Server::setup() {
   FPT_HIP(hipSetDevice(device));
   FPT_HIP(hipHostMalloc((void**)&h_ctr, sizeof(Counters), hipHostMallocDefault));
   FPT_HIP(hipHostMalloc((void**)&h_mom, sizeof(MomDev) * kMaxSets, hipHostMallocDefault));
-  FPT_HIP(hipEventCreate(&ev0));
-  FPT_HIP(hipEventCreate(&ev1));
   const SliceArgs a = args();
   FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(a.ctr), sizeof(Counters) / 8,
                           0ull, stream));
@@ -310,8 +307,11 @@ void Server::finish_locked(Job* j, const MomDev& m) {
     if (hipMemcpyAsync(j->counts.data(), pool + off_hist + 8 * j->hist_off,
                        8 * (size_t)j->params.n_bins, hipMemcpyDeviceToHost,
                        stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess)
+        hipStreamSynchronize(stream) != hipSuccess) {
+      // the device is in doubt: stop the loop (pending polls report it)
       thread_error = "histogram readback failed";
+      stop = true;
+    }
   }
   fill_moments(m, j->params.dt, &j->mom);
   hist_alloc.release(j->hist_off, (uint64_t)j->params.n_bins);
@@ -333,10 +333,8 @@ fpt_status Server::step() {
     buf_seen = buf;
   }
   const uint32_t groups = (uint32_t)(a.n_lanes / kBlockThreads);
-  FPT_HIP(hipEventRecord(ev0, stream));
   FPT_HIP(launch_slice(precision == FPT_FP64, model, tuning.replicas_per_lane, true, a, groups,
                        stream));
-  FPT_HIP(hipEventRecord(ev1, stream));
   if (a.whole_waves && cursor_seen < a.total) {
     // the active slots into set order, the free ones past them refilled in
     // queue order (lanes of a wavefront share a set again)
@@ -574,8 +572,6 @@ void fpt_server_destroy(fpt_server_t server) {
   (void)hipStreamSynchronize(s->stream);
   if (s->h_ctr) (void)hipHostFree(s->h_ctr);
   if (s->h_mom) (void)hipHostFree(s->h_mom);
-  if (s->ev0) (void)hipEventDestroy(s->ev0);
-  if (s->ev1) (void)hipEventDestroy(s->ev1);
   delete s;
   delete server;
 }
