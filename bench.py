@@ -837,18 +837,29 @@ def main():
                                        if kernel_s > 0 and mix_attainable() else None),
             "avg_launch_ms": st["kernel_ms"] / launches, "launches": st["n_launches"]}
 
+    def side_leg(name, fn):
+        # a leg beside the headline: a library error there is reported in its
+        # field and does not take the measured line with it
+        try:
+            return fn()
+        except Exception as e:  # noqa: BLE001
+            print(f"[bench] {name} leg failed: {type(e).__name__}: {e}", file=sys.stderr,
+                  flush=True)
+            return {"error": f"{type(e).__name__}: {e}"}
+
     batched = None
     if not args.no_batched:
-        batched = batched_leg()
-        print(f"[bench] batched: {batched['replica_steps_per_s']:.4e} replica-steps/s, "
-              f"{batched['launches']} launches", file=sys.stderr, flush=True)
+        batched = side_leg("batched", batched_leg)
+        if "error" not in batched:
+            print(f"[bench] batched: {batched['replica_steps_per_s']:.4e} replica-steps/s, "
+                  f"{batched['launches']} launches", file=sys.stderr, flush=True)
 
-    latency = serving_legs(args, value)
+    latency = side_leg("serving", lambda: serving_legs(args, value))
 
     cpu = None
     if args.cpu_replicas > 0:
         procs = args.cpu_procs or min(16, os.cpu_count() or 1)
-        cpu = cpu_baseline(args.cpu_replicas, procs)
+        cpu = side_leg("cpu_baseline", lambda: cpu_baseline(args.cpu_replicas, procs))
 
     line = {
         "metric": METRIC, "value": value, "unit": "replica-steps/s", "n_gpus": 1,
