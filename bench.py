@@ -120,7 +120,7 @@ def parse():
     ap.add_argument("--fp64-replicas", type=int, default=2 ** 18,
                     help="replicas of the FP64 comparison leg (independent seed); 0 runs "
                          "the FP32C leg alone and prints its figures only")
-    ap.add_argument("--cpu-replicas", type=int, default=32,
+    ap.add_argument("--cpu-replicas", type=int, default=64,
                     help="replicas of the oracle CPU-baseline sample (0: skip)")
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle processes (0: min(16, host cores))")
