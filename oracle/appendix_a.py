@@ -1,6 +1,6 @@
 """Appendix A of arXiv:1802.05065: the statistical model of parallel execution.
 
-TEST INFRASTRUCTURE ONLY (used to judge the measured lane utilisation of the
+TEST INFRASTRUCTURE ONLY (used to assess the measured lane utilisation of the
 one-replica-per-lane and refill schedules).
 
 Model (Appendix A, Eqs. (A.1)-(A.5)): each run's execution time is an
