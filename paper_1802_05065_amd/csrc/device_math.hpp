@@ -12,6 +12,7 @@
 
 #include <cstdint>
 
+#include "f64_math.hpp"
 #include "internal.hpp"
 
 namespace fpt {
@@ -92,10 +93,10 @@ __device__ __forceinline__ void normals_f64(const Words& w, double z[4]) {
   for (int pair = 0; pair < 2; ++pair) {
     const double a = ((double)x[2 * pair] + 0.5) * 0x1p-32;
     const double b = ((double)x[2 * pair + 1] + 0.5) * 0x1p-32;
-    const double radius = sqrt(-2.0 * log(a));
+    const double radius = sqrt(f64m::minus_two_log(a));
     const double angle = 2.0 * kPi * b;
     double s, c;
-    sincos(angle, &s, &c);
+    f64m::sincos_f64(angle, &s, &c);
     z[2 * pair] = radius * c;
     z[2 * pair + 1] = radius * s;
   }
@@ -181,7 +182,7 @@ __device__ __forceinline__ void step_f64_under(const ParF64& p, double kd,
                                                double& v) {
   const double gamma_k = p.gamma0 + p.dgamma * kd;
   const double phi_new = phi + p.dt * v;
-  const double force = -p.alpha * v - p.V0 * sin(phi) + p.V0 * gamma_k;
+  const double force = -p.alpha * v - p.V0 * f64m::sin_f64(phi) + p.V0 * gamma_k;
   v = v + p.dt * force + p.sigma * r;
   phi = phi_new;
 }
@@ -192,7 +193,7 @@ __device__ __forceinline__ void step_f64_under_si(const ParF64& p, double kd,
                                                   double r, double& phi,
                                                   double& v) {
   const double gamma_k = p.gamma0 + p.dgamma * kd;
-  const double force = -p.alpha * v - p.V0 * sin(phi) + p.V0 * gamma_k;
+  const double force = -p.alpha * v - p.V0 * f64m::sin_f64(phi) + p.V0 * gamma_k;
   v = v + p.dt * force + p.sigma * r;
   phi = phi + p.dt * v;
 }
@@ -201,7 +202,7 @@ __device__ __forceinline__ void step_f64_under_si(const ParF64& p, double kd,
 __device__ __forceinline__ void step_f64_over(const ParF64& p, double kd,
                                               double r, double& phi) {
   const double gamma_k = p.gamma0 + p.dgamma * kd;
-  const double drift = -p.V0 * sin(phi) + gamma_k;
+  const double drift = -p.V0 * f64m::sin_f64(phi) + gamma_k;
   phi = phi + p.dt * drift + p.sigma * r;
 }
 

@@ -1,0 +1,129 @@
+// f64_math.hpp -- double-precision sine / cosine and the Box-Muller log of
+// the FP64 integrator, written for the arguments it sees: phases of moderate
+// size, angles in (0, 2 pi), uniforms in (0, 1).  No special-case handling
+// beyond a fallback to the general library routines for phases of 2^20
+// radians or more (and NaN).  Errors stay within a few units in the last
+// place of the correctly rounded values (checked on the host against the C
+// library by tests/test_f64_math_host.py).
+//
+// Methods: Cody and Waite's additive reduction by pi/2 with the constant
+// split in three parts (W. J. Cody, W. Waite, "Software Manual for the
+// Elementary Functions", 1980), the Taylor series of sin and cos on
+// [-pi/4, pi/4], and ln m = 2 atanh((m - 1)/(m + 1)) on [sqrt(2)/2, sqrt(2))
+// by its odd power series.  Coefficients are 1/n! and 1/n rounded to double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace fpt {
+namespace f64m {
+
+constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+// pi/2 = kPio2a + kPio2b + kPio2c to 1e-37; the first two carry 33
+// significant bits, so n kPio2a and n kPio2b are exact for |n| < 2^20
+constexpr double kPio2a = 0x1.921fb54400000p+0;
+constexpr double kPio2b = 0x1.0b4611a600000p-34;
+constexpr double kPio2c = 0x1.3198a2e037073p-69;
+constexpr double kReduceLimit = 0x1p20;
+
+// ln 2 = kLn2a + kLn2b to 1e-27; kLn2a carries 32 significant bits, so
+// e kLn2a is exact for the exponents of (0, 1)
+constexpr double kLn2a = 0x1.62e42ff000000p-1;
+constexpr double kLn2b = -0x1.718432a1b0e26p-35;
+constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;
+
+// sin r and cos r for |r| <= pi/4 (plus the reduction's slack): Taylor
+// polynomials through r^17 and r^16, whose next terms stay below 2^-62 and
+// 2^-58 of the result there
+__host__ __device__ __forceinline__ void sincos_poly(double r, double& s, double& c) {
+  const double z = r * r;
+  double ps = 0x1.952c77030ad4ap-49;         //  1/17!
+  ps = fma(ps, z, -0x1.ae7f3e733b81fp-41);   // -1/15!
+  ps = fma(ps, z, 0x1.6124613a86d09p-33);    //  1/13!
+  ps = fma(ps, z, -0x1.ae64567f544e4p-26);   // -1/11!
+  ps = fma(ps, z, 0x1.71de3a556c734p-19);    //  1/9!
+  ps = fma(ps, z, -0x1.a01a01a01a01ap-13);   // -1/7!
+  ps = fma(ps, z, 0x1.1111111111111p-7);     //  1/5!
+  ps = fma(ps, z, -0x1.5555555555555p-3);    // -1/3!
+  s = fma(r * z, ps, r);
+  double pc = 0x1.ae7f3e733b81fp-45;         //  1/16!
+  pc = fma(pc, z, -0x1.93974a8c07c9dp-37);   // -1/14!
+  pc = fma(pc, z, 0x1.1eed8eff8d898p-29);    //  1/12!
+  pc = fma(pc, z, -0x1.27e4fb7789f5cp-22);   // -1/10!
+  pc = fma(pc, z, 0x1.a01a01a01a01ap-16);    //  1/8!
+  pc = fma(pc, z, -0x1.6c16c16c16c17p-10);   // -1/6!
+  pc = fma(pc, z, 0x1.5555555555555p-5);     //  1/4!
+  pc = fma(pc, z, -0.5);                     // -1/2!
+  c = fma(z, pc, 1.0);
+}
+
+// x = q pi/2 + r with |r| <= pi/4 (|x| < 2^20): the first subtraction is
+// exact, the other two round once each
+__host__ __device__ __forceinline__ double reduce_pio2(double x, int& q) {
+  const double n = rint(x * kTwoOverPi);
+  double r = fma(-n, kPio2a, x);
+  r = fma(-n, kPio2b, r);
+  r = fma(-n, kPio2c, r);
+  q = (int)n;
+  return r;
+}
+
+// Any finite x (the general routine beyond 2^20).
+__host__ __device__ __forceinline__ double sin_f64(double x) {
+  if (!(fabs(x) < kReduceLimit)) return ::sin(x);
+  int q;
+  const double r = reduce_pio2(x, q);
+  double ps, pc;
+  sincos_poly(r, ps, pc);
+  const double v = (q & 1) ? pc : ps;
+  return (q & 2) ? -v : v;
+}
+
+// Both at once, for |x| < 2^20 only (the Box-Muller angles lie in
+// (0, 2 pi)); no fallback.
+__host__ __device__ __forceinline__ void sincos_f64(double x, double* s, double* c) {
+  int q;
+  const double r = reduce_pio2(x, q);
+  double ps, pc;
+  sincos_poly(r, ps, pc);
+  const double vs = (q & 1) ? pc : ps;
+  const double vc = (q & 1) ? ps : pc;
+  *s = (q & 2) ? -vs : vs;
+  *c = ((q + 1) & 2) ? -vc : vc;
+}
+
+// -2 ln a for a normal number in (0, 1]: a = m 2^e with m in
+// [sqrt(2)/2, sqrt(2)), ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^21/21)
+// with s = (m - 1)/(m + 1), |s| <= 0.172 (next term below 2^-60 of ln m)
+__host__ __device__ __forceinline__ double minus_two_log(double a) {
+  int e;
+  double m = frexp(a, &e);
+  if (m < kSqrtHalf) {
+    m = 2.0 * m;
+    --e;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  double p = 0x1.8618618618618p-5;   // 1/21
+  p = fma(p, z, 0x1.af286bca1af28p-5);  // 1/19
+  p = fma(p, z, 0x1.e1e1e1e1e1e1ep-5);  // 1/17
+  p = fma(p, z, 0x1.1111111111111p-4);  // 1/15
+  p = fma(p, z, 0x1.3b13b13b13b14p-4);  // 1/13
+  p = fma(p, z, 0x1.745d1745d1746p-4);  // 1/11
+  p = fma(p, z, 0x1.c71c71c71c71cp-4);  // 1/9
+  p = fma(p, z, 0x1.2492492492492p-3);  // 1/7
+  p = fma(p, z, 0x1.999999999999ap-3);  // 1/5
+  p = fma(p, z, 0x1.5555555555555p-2);  // 1/3
+  const double t = 2.0 * s;
+  const double de = (double)e;
+  // ln a = e ln2 + t + t z p, the small parts summed first
+  const double lo = fma(de, kLn2b, (t * z) * p);
+  const double ln_a = fma(de, kLn2a, t + lo);
+  return -2.0 * ln_a;
+}
+
+}  // namespace f64m
+}  // namespace fpt
