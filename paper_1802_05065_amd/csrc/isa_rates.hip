@@ -7,13 +7,17 @@
 // instruction's throughput.  Rates are printed absolute (lane-ops/s) and
 // relative to v_fma_f32, i.e. each instruction's cost in v_fma_f32 issue
 // slots.  "pair" tests issue two different instructions per chain step to
-// show whether they overlap (cost of the pair < sum of the two).
+// show whether they overlap (cost of the pair < sum of the two); the
+// "cross-wave" line does the same with the two instructions in different
+// waves of the SIMD.
 //
 // usage: isa_rates
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 
 #define CHECK(x)                                                          \
   do {                                                                    \
@@ -105,6 +109,32 @@ struct Entry {
 #define ENTRY(name, text, n) {#name, k_##name, n, 0.0},
 static Entry g_entries[] = {OP_LIST(ENTRY)};
 
+// Cross-wave overlap: the even waves of each workgroup run v_sin_f32 chains
+// and the odd ones v_fmac_f32 chains, as many steps each.  If the SIMD
+// issued a transcendental of one wave beside a VALU instruction of another,
+// the launch would take as long as its slower half; if they share the issue
+// slots, as long as the two halves one after the other.
+__global__ __launch_bounds__(kThreads) void k_split_sin_fmac(float* out, float seed) {
+  const uint32_t t = blockIdx.x * kThreads + threadIdx.x;
+  float x[kChains];
+  const float p = 0.999f + 1e-9f * seed;
+  for (int c = 0; c < kChains; ++c) x[c] = 0.25f + 1e-7f * (float)(t + c);
+  if (((threadIdx.x / 64) & 1) == 0) {
+    for (int i = 0; i < kIters; ++i) {
+      _Pragma("unroll") for (int c = 0; c < kChains; ++c)
+        asm volatile("v_sin_f32 %[x], %[x]" : [x] "+v"(x[c]));
+    }
+  } else {
+    for (int i = 0; i < kIters; ++i) {
+      _Pragma("unroll") for (int c = 0; c < kChains; ++c)
+        asm volatile("v_fmac_f32 %[x], %[ps], %[x]" : [x] "+v"(x[c]) : [ps] "s"(p));
+    }
+  }
+  float acc = 0.f;
+  for (int c = 0; c < kChains; ++c) acc += x[c];
+  out[t] = acc;
+}
+
 static int measure(Entry& e, float* out, int groups, hipEvent_t e0, hipEvent_t e1) {
   hipLaunchKernelGGL(e.kernel, dim3(groups), dim3(kThreads), 0, 0, out, 1.0f);
   CHECK(hipGetLastError());
@@ -133,6 +163,13 @@ int main() {
   const int n = (int)(sizeof(g_entries) / sizeof(g_entries[0]));
   for (int i = 0; i < n; ++i)
     if (measure(g_entries[i], out, groups, e0, e1)) return 1;
+  Entry split{"split_sin_fmac", k_split_sin_fmac, 1, 0.0};
+  if (measure(split, out, groups, e0, e1)) return 1;
+  Entry sin_only{}, fmac_only{};
+  for (int i = 0; i < n; ++i) {
+    if (std::strcmp(g_entries[i].name, "sin_f32") == 0) sin_only = g_entries[i];
+    if (std::strcmp(g_entries[i].name, "fmac_f32_s") == 0) fmac_only = g_entries[i];
+  }
   const double fma_rate = g_entries[0].rate;
   std::printf("gfx950 VALU issue rates: %d CUs, 8 waves/SIMD, %d chains x %d steps per lane\n",
               cus, kChains, kIters);
@@ -143,6 +180,13 @@ int main() {
                 g_entries[i].rate * 1e-12, fma_rate / g_entries[i].rate);
   std::printf("v_fma_f32: %.2f T lane-op/s = %.1f lane-ops per CU per ns\n", fma_rate * 1e-12,
               fma_rate / cus * 1e-9);
+  // times per lane-instruction, relative to the split launch's
+  const double t_split = 1.0 / split.rate;
+  const double t_serial = 0.5 / sin_only.rate + 0.5 / fmac_only.rate;
+  const double t_overlap = std::max(0.5 / sin_only.rate, 0.5 / fmac_only.rate);
+  std::printf("cross-wave: even waves v_sin_f32, odd waves v_fmac_f32 (s): %.2f T lane-op/s; "
+              "time %.3f of the halves one after the other, %.3f of the slower half alone\n",
+              split.rate * 1e-12, t_split / t_serial, t_split / t_overlap);
   CHECK(hipFree(out));
   return 0;
 }
