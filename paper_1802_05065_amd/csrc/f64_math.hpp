@@ -2,15 +2,16 @@
 // the FP64 integrator, written for the arguments it sees: phases of moderate
 // size, angles in (0, 2 pi), uniforms in (0, 1).  No special-case handling
 // beyond a fallback to the general library routines for phases of 2^20
-// radians or more (and NaN).  Errors stay within a few units in the last
+// radians or more (and NaN).  Errors stay within about 2 units in the last
 // place of the correctly rounded values (checked on the host against the C
 // library by tests/test_f64_math_host.py).
 //
-// Methods: Cody and Waite's additive reduction by pi/2 with the constant
-// split in three parts (W. J. Cody, W. Waite, "Software Manual for the
-// Elementary Functions", 1980), the Taylor series of sin and cos on
-// [-pi/4, pi/4], and ln m = 2 atanh((m - 1)/(m + 1)) on [sqrt(2)/2, sqrt(2))
-// by its odd power series.  Coefficients are 1/n! and 1/n rounded to double.
+// Methods: Cody and Waite's additive reduction by pi (sin) or pi/2 (sin and
+// cos together) with the constant split in three parts (W. J. Cody, W.
+// Waite, "Software Manual for the Elementary Functions", 1980), the Taylor
+// series of sin on [-pi/2, pi/2] and of sin and cos on [-pi/4, pi/4], and
+// ln m = 2 atanh((m - 1)/(m + 1)) on [sqrt(2)/2, sqrt(2)) by its odd power
+// series.  Coefficients are 1/n! and 1/n rounded to double.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -71,15 +72,34 @@ __host__ __device__ __forceinline__ double reduce_pio2(double x, int& q) {
   return r;
 }
 
-// Any finite x (the general routine beyond 2^20).
+// sin x for any finite x (the general routine from 2^20 on): x = n pi + r
+// with |r| <= pi/2 (pi split as pi/2 above), sin x = (-1)^n sin r, and sin r
+// by its Taylor polynomial through r^21 (next term below 2^-59 of the
+// result), one polynomial and no quadrant selection
+constexpr double kOneOverPi = 0x1.45f306dc9c883p-2;
+constexpr double kPia = 0x1.921fb54400000p+1;
+constexpr double kPib = 0x1.0b4611a600000p-33;
+constexpr double kPic = 0x1.3198a2e037073p-68;
+
 __host__ __device__ __forceinline__ double sin_f64(double x) {
   if (!(fabs(x) < kReduceLimit)) return ::sin(x);
-  int q;
-  const double r = reduce_pio2(x, q);
-  double ps, pc;
-  sincos_poly(r, ps, pc);
-  const double v = (q & 1) ? pc : ps;
-  return (q & 2) ? -v : v;
+  const double n = rint(x * kOneOverPi);
+  double r = fma(-n, kPia, x);
+  r = fma(-n, kPib, r);
+  r = fma(-n, kPic, r);
+  const double z = r * r;
+  double p = 0x1.71b8ef6dcf572p-66;          //  1/21!
+  p = fma(p, z, -0x1.2f49b46814157p-57);     // -1/19!
+  p = fma(p, z, 0x1.952c77030ad4ap-49);      //  1/17!
+  p = fma(p, z, -0x1.ae7f3e733b81fp-41);     // -1/15!
+  p = fma(p, z, 0x1.6124613a86d09p-33);      //  1/13!
+  p = fma(p, z, -0x1.ae64567f544e4p-26);     // -1/11!
+  p = fma(p, z, 0x1.71de3a556c734p-19);      //  1/9!
+  p = fma(p, z, -0x1.a01a01a01a01ap-13);     // -1/7!
+  p = fma(p, z, 0x1.1111111111111p-7);       //  1/5!
+  p = fma(p, z, -0x1.5555555555555p-3);      // -1/3!
+  const double s = fma(r * z, p, r);
+  return ((int)n & 1) ? -s : s;
 }
 
 // Both at once, for |x| < 2^20 only (the Box-Muller angles lie in

@@ -5,6 +5,7 @@
 #include <cinttypes>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "../paper_1802_05065_amd/csrc/f64_math.hpp"
@@ -49,8 +50,8 @@ void report(const char* name, const Worst& w, long n) {
 
 }  // namespace
 
-int main() {
-  const long n = 2000000;
+int main(int argc, char** argv) {
+  const long n = argc > 1 ? atol(argv[1]) : 2000000;
   // sin of phases: moderate arguments, and points next to multiples of pi/2
   {
     Worst w;
