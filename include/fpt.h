@@ -77,7 +77,9 @@ typedef enum { FPT_UNDERDAMPED = 0, FPT_OVERDAMPED = 1 } fpt_model;
  * same cost).  Underdamped model only. */
 typedef enum { FPT_EXPLICIT = 0, FPT_SEMI_IMPLICIT = 1 } fpt_scheme;
 
-/* FPT_FP64: every replica operation in FP64 (the plain path).
+/* FPT_FP64: every replica operation in FP64 (the plain path); sin, the
+ * Box-Muller log and sin/cos within about 2 ulp of their correctly rounded
+ * values.
  * FPT_FP32C: replica state in FP32 with a compensated phase (a float pair
  * between 4-step blocks; each block's advance, summed in FP32, is added with
  * Kahan's compensation); FP64 is kept for gamma_k from the exact integer
