@@ -161,7 +161,8 @@ typedef struct fpt_tuning {
 /* Per-set results.  Moments are over escaped replicas; times in units of t. */
 typedef struct fpt_moments {
   uint64_t n_escaped, n_censored, n_overflow;
-  uint64_t sum_k;                 /* sum of escape steps */
+  uint64_t sum_k;                 /* sum of escape steps (exact while
+                                     n_escaped * max_steps < 2^64) */
   uint64_t sum_k2_lo, sum_k2_hi;  /* 128-bit sum of squared escape steps */
   double mean_t, se_t;            /* dt*mean(k), dt*stddev(k)/sqrt(n) */
 } fpt_moments;
