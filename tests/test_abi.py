@@ -235,3 +235,17 @@ def test_header_is_pedantic_c99_and_cxx(tmp_path):
                  "-fsyntax-only", "-x", "c++", "-I" + inc, str(src)]):
         res = subprocess.run(cmd, capture_output=True, text=True)
         assert res.returncode == 0, res.stderr
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # no CPU fallback: without libfpt.so every entry point raises
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libfpt.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.fpt_plan([workloads.plain_escape()], "fp64")
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.fpt_api_version()
+    from paper_1802_05065_amd import api
+
+    with pytest.raises(Exception):
+        api.simulate(workloads.plain_escape(n_replicas=16), "fp64")
