@@ -36,28 +36,42 @@ constexpr double kLn2a = 0x1.62e42ff000000p-1;
 constexpr double kLn2b = -0x1.718432a1b0e26p-35;
 constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;
 
+// One Horner step p z + c as a single three-operand v_fma_f64 with the
+// coefficient kept in registers: written as fma(), the compiler turns each
+// step into a copy of c plus the two-operand fma that overwrites its addend.
+// (Host builds use fma().)
+__host__ __device__ __forceinline__ double horner(double p, double z, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "v"(c));
+  return r;
+#else
+  return fma(p, z, c);
+#endif
+}
+
 // sin r and cos r for |r| <= pi/4 (plus the reduction's slack): Taylor
 // polynomials through r^17 and r^16, whose next terms stay below 2^-62 and
 // 2^-58 of the result there
 __host__ __device__ __forceinline__ void sincos_poly(double r, double& s, double& c) {
   const double z = r * r;
   double ps = 0x1.952c77030ad4ap-49;         //  1/17!
-  ps = fma(ps, z, -0x1.ae7f3e733b81fp-41);   // -1/15!
-  ps = fma(ps, z, 0x1.6124613a86d09p-33);    //  1/13!
-  ps = fma(ps, z, -0x1.ae64567f544e4p-26);   // -1/11!
-  ps = fma(ps, z, 0x1.71de3a556c734p-19);    //  1/9!
-  ps = fma(ps, z, -0x1.a01a01a01a01ap-13);   // -1/7!
-  ps = fma(ps, z, 0x1.1111111111111p-7);     //  1/5!
-  ps = fma(ps, z, -0x1.5555555555555p-3);    // -1/3!
+  ps = horner(ps, z, -0x1.ae7f3e733b81fp-41);   // -1/15!
+  ps = horner(ps, z, 0x1.6124613a86d09p-33);    //  1/13!
+  ps = horner(ps, z, -0x1.ae64567f544e4p-26);   // -1/11!
+  ps = horner(ps, z, 0x1.71de3a556c734p-19);    //  1/9!
+  ps = horner(ps, z, -0x1.a01a01a01a01ap-13);   // -1/7!
+  ps = horner(ps, z, 0x1.1111111111111p-7);     //  1/5!
+  ps = horner(ps, z, -0x1.5555555555555p-3);    // -1/3!
   s = fma(r * z, ps, r);
   double pc = 0x1.ae7f3e733b81fp-45;         //  1/16!
-  pc = fma(pc, z, -0x1.93974a8c07c9dp-37);   // -1/14!
-  pc = fma(pc, z, 0x1.1eed8eff8d898p-29);    //  1/12!
-  pc = fma(pc, z, -0x1.27e4fb7789f5cp-22);   // -1/10!
-  pc = fma(pc, z, 0x1.a01a01a01a01ap-16);    //  1/8!
-  pc = fma(pc, z, -0x1.6c16c16c16c17p-10);   // -1/6!
-  pc = fma(pc, z, 0x1.5555555555555p-5);     //  1/4!
-  pc = fma(pc, z, -0.5);                     // -1/2!
+  pc = horner(pc, z, -0x1.93974a8c07c9dp-37);   // -1/14!
+  pc = horner(pc, z, 0x1.1eed8eff8d898p-29);    //  1/12!
+  pc = horner(pc, z, -0x1.27e4fb7789f5cp-22);   // -1/10!
+  pc = horner(pc, z, 0x1.a01a01a01a01ap-16);    //  1/8!
+  pc = horner(pc, z, -0x1.6c16c16c16c17p-10);   // -1/6!
+  pc = horner(pc, z, 0x1.5555555555555p-5);     //  1/4!
+  pc = horner(pc, z, -0.5);                     // -1/2!
   c = fma(z, pc, 1.0);
 }
 
@@ -89,15 +103,15 @@ __host__ __device__ __forceinline__ double sin_f64(double x) {
   r = fma(-n, kPic, r);
   const double z = r * r;
   double p = 0x1.71b8ef6dcf572p-66;          //  1/21!
-  p = fma(p, z, -0x1.2f49b46814157p-57);     // -1/19!
-  p = fma(p, z, 0x1.952c77030ad4ap-49);      //  1/17!
-  p = fma(p, z, -0x1.ae7f3e733b81fp-41);     // -1/15!
-  p = fma(p, z, 0x1.6124613a86d09p-33);      //  1/13!
-  p = fma(p, z, -0x1.ae64567f544e4p-26);     // -1/11!
-  p = fma(p, z, 0x1.71de3a556c734p-19);      //  1/9!
-  p = fma(p, z, -0x1.a01a01a01a01ap-13);     // -1/7!
-  p = fma(p, z, 0x1.1111111111111p-7);       //  1/5!
-  p = fma(p, z, -0x1.5555555555555p-3);      // -1/3!
+  p = horner(p, z, -0x1.2f49b46814157p-57);     // -1/19!
+  p = horner(p, z, 0x1.952c77030ad4ap-49);      //  1/17!
+  p = horner(p, z, -0x1.ae7f3e733b81fp-41);     // -1/15!
+  p = horner(p, z, 0x1.6124613a86d09p-33);      //  1/13!
+  p = horner(p, z, -0x1.ae64567f544e4p-26);     // -1/11!
+  p = horner(p, z, 0x1.71de3a556c734p-19);      //  1/9!
+  p = horner(p, z, -0x1.a01a01a01a01ap-13);     // -1/7!
+  p = horner(p, z, 0x1.1111111111111p-7);       //  1/5!
+  p = horner(p, z, -0x1.5555555555555p-3);      // -1/3!
   const double s = fma(r * z, p, r);
   return ((int)n & 1) ? -s : s;
 }
@@ -128,15 +142,15 @@ __host__ __device__ __forceinline__ double minus_two_log(double a) {
   const double s = (m - 1.0) / (m + 1.0);
   const double z = s * s;
   double p = 0x1.8618618618618p-5;   // 1/21
-  p = fma(p, z, 0x1.af286bca1af28p-5);  // 1/19
-  p = fma(p, z, 0x1.e1e1e1e1e1e1ep-5);  // 1/17
-  p = fma(p, z, 0x1.1111111111111p-4);  // 1/15
-  p = fma(p, z, 0x1.3b13b13b13b14p-4);  // 1/13
-  p = fma(p, z, 0x1.745d1745d1746p-4);  // 1/11
-  p = fma(p, z, 0x1.c71c71c71c71cp-4);  // 1/9
-  p = fma(p, z, 0x1.2492492492492p-3);  // 1/7
-  p = fma(p, z, 0x1.999999999999ap-3);  // 1/5
-  p = fma(p, z, 0x1.5555555555555p-2);  // 1/3
+  p = horner(p, z, 0x1.af286bca1af28p-5);  // 1/19
+  p = horner(p, z, 0x1.e1e1e1e1e1e1ep-5);  // 1/17
+  p = horner(p, z, 0x1.1111111111111p-4);  // 1/15
+  p = horner(p, z, 0x1.3b13b13b13b14p-4);  // 1/13
+  p = horner(p, z, 0x1.745d1745d1746p-4);  // 1/11
+  p = horner(p, z, 0x1.c71c71c71c71cp-4);  // 1/9
+  p = horner(p, z, 0x1.2492492492492p-3);  // 1/7
+  p = horner(p, z, 0x1.999999999999ap-3);  // 1/5
+  p = horner(p, z, 0x1.5555555555555p-2);  // 1/3
   const double t = 2.0 * s;
   const double de = (double)e;
   // ln a = e ln2 + t + t z p, the small parts summed first
