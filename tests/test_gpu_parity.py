@@ -103,10 +103,11 @@ def test_trajectory_fp64_matches_oracle(maker):
     np.testing.assert_allclose(phi[:50], rphi[:50], rtol=1e-15, atol=0)
 
 
-@pytest.mark.parametrize("phi0", [1e5 + 0.3, 2.0 ** 21 + 0.3])
+@pytest.mark.parametrize("phi0", [1e5 + 0.3, 2.0 ** 21 + 0.3, 2.0 ** 31 + 0.3])
 def test_trajectory_fp64_far_phase_matches_oracle(phi0):
     # phases far from 0: the FP64 sine's reduction by pi with a large
-    # multiple (1e5), and past 2^20 rad the general routine it falls back to
+    # multiple (1e5), past 2^20 rad (its first step rounds) and past 2^30
+    # (first reduced in a pass of its own)
     p = dict(workloads.plain_escape(n_replicas=4), phi0=phi0, threshold=1e300)
     phi, v = api.trajectory(p, replica=1, n_steps=3001, precision="fp64")
     rphi, rv = oracle.trajectory(_op(p), 1, 3001)
