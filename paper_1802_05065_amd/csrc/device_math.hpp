@@ -93,7 +93,7 @@ __device__ __forceinline__ void normals_f64(const Words& w, double z[4]) {
   for (int pair = 0; pair < 2; ++pair) {
     const double a = ((double)x[2 * pair] + 0.5) * 0x1p-32;
     const double b = ((double)x[2 * pair + 1] + 0.5) * 0x1p-32;
-    const double radius = sqrt(f64m::minus_two_log(a));
+    const double radius = f64m::sqrt_positive(f64m::minus_two_log(a));
     const double angle = 2.0 * kPi * b;
     double s, c;
     f64m::sincos_f64(angle, &s, &c);

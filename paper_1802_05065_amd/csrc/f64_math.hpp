@@ -140,6 +140,55 @@ __host__ __device__ __forceinline__ void sincos_f64(double x, double* s, double*
   *c = ((q + 1) & 2) ? -vc : vc;
 }
 
+// Reciprocal and square root for the Box-Muller radius, where the operands
+// are positive normal numbers of moderate size: the hardware estimate
+// (v_rcp_f64 / v_rsq_f64) refined by Newton-Raphson steps, without the
+// scaling and special-case handling of the general division and sqrt.
+// (Host builds start from a float estimate, coarser than the hardware's,
+// so the host check covers the refinement.)
+__host__ __device__ __forceinline__ double rcp_estimate(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcp(d);
+#else
+  return (double)(1.0f / (float)d);
+#endif
+}
+
+__host__ __device__ __forceinline__ double rsq_estimate(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsq(x);
+#else
+  return (double)(1.0f / std::sqrt((float)x));
+#endif
+}
+
+// n / d for d in [1, 4): two Newton-Raphson steps on 1/d, then the quotient
+// corrected once by its residual
+__host__ __device__ __forceinline__ double div_moderate(double n, double d) {
+  double y = rcp_estimate(d);
+  double e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  const double q = n * y;
+  return fma(fma(-q, d, n), y, q);
+}
+
+// sqrt(x) for normal x > 0: from r ~ 1/sqrt(x), g = x r and h = r/2 refined
+// together (Goldschmidt), then g corrected by its residual, twice
+__host__ __device__ __forceinline__ double sqrt_positive(double x) {
+  const double r = rsq_estimate(x);
+  double g = x * r;
+  double h = 0.5 * r;
+  const double t = fma(-g, h, 0.5);
+  g = fma(g, t, g);
+  h = fma(h, t, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // -2 ln a for a normal number in (0, 1]: a = m 2^e with m in
 // [sqrt(2)/2, sqrt(2)), ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^21/21)
 // with s = (m - 1)/(m + 1), |s| <= 0.172 (next term below 2^-60 of ln m)
@@ -150,7 +199,7 @@ __host__ __device__ __forceinline__ double minus_two_log(double a) {
     m = 2.0 * m;
     --e;
   }
-  const double s = (m - 1.0) / (m + 1.0);
+  const double s = div_moderate(m - 1.0, m + 1.0);
   const double z = s * s;
   double p = 0x1.8618618618618p-5;   // 1/21
   p = horner(p, z, 0x1.af286bca1af28p-5);  // 1/19

@@ -107,6 +107,16 @@ int main(int argc, char** argv) {
       w.add(ulps(fpt::f64m::minus_two_log(a), -2.0L * std::log((long double)a)), a);
     }
     report("minus_two_log", w, n);
+    Worst r;
+    for (long i = 0; i < n; ++i) {
+      uint32_t x = (uint32_t)next_u64();
+      if (i < 64) x = (uint32_t)i;
+      if (i >= 64 && i < 128) x = 0xFFFFFFFFu - (uint32_t)(i - 64);
+      const double a = ((double)x + 0.5) * 0x1p-32;
+      const double l = fpt::f64m::minus_two_log(a);
+      r.add(ulps(fpt::f64m::sqrt_positive(l), std::sqrt((long double)l)), l);
+    }
+    report("radius_sqrt", r, n);
   }
   return 0;
 }

@@ -20,7 +20,8 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 # (with 2e7 arguments per range: 1.93, 2.02, 2.38 for the three sin ranges)
 # and, for phases of 2^30 to 2^41 rad (reduced in two passes), SIN_FAR
 BOUNDS = {"sin_moderate": 2.5, "sin_near_zeros": 2.5, "sin_large": 3.0, "sin_far": 3.0,
-          "sincos_angle_sin": 2.0, "sincos_angle_cos": 2.0, "minus_two_log": 2.0}
+          "sincos_angle_sin": 2.0, "sincos_angle_cos": 2.0, "minus_two_log": 2.0,
+          "radius_sqrt": 1.0}
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
