@@ -48,6 +48,19 @@ __host__ __device__ __forceinline__ double horner(double p, double z, double c) 
 #endif
 }
 
+// x with its sign flipped when bit 0 of `bits` is set (an xor of the sign
+// bit: no select)
+__host__ __device__ __forceinline__ double flip_sign(double x, uint32_t bits) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, x) ^ ((uint64_t)(bits & 1u) << 63));
+}
+
+// The low bits of an integer-valued double n with |n| < 2^51: n + 1.5 2^52
+// lies in [2^52, 2^53), where the significand's last bit is worth 1, and
+// holds n in its low bits (two's complement for n < 0)
+__host__ __device__ __forceinline__ uint32_t low_bits(double n) {
+  return (uint32_t)__builtin_bit_cast(uint64_t, n + 0x1.8p52);
+}
+
 // sin r and cos r for |r| <= pi/4 (plus the reduction's slack): Taylor
 // polynomials through r^17 and r^16, whose next terms stay below 2^-62 and
 // 2^-58 of the result there
@@ -91,8 +104,9 @@ __host__ __device__ __forceinline__ double reduce_pio2(double x, int& q) {
 // about 2 ulp; beyond, that step rounds once, and from 2^30 rad on the phase
 // is first brought below pi the same way (random phases stay within 2.3 ulp
 // up to 2^41 rad, measured; next to multiples of pi the error is absolute,
-// far below the phase's own ulp).  No general library routine: one beside
-// it costs the integrator registers it then spills.
+// far below the phase's own ulp; past 2^52 rad, where the phase's ulp
+// exceeds 1, the result means nothing).  No general library routine: one
+// beside it costs the integrator registers it then spills.
 constexpr double kOneOverPi = 0x1.45f306dc9c883p-2;
 constexpr double kPia = 0x1.921fb54400000p+1;
 constexpr double kPib = 0x1.0b4611a600000p-33;
@@ -105,7 +119,7 @@ __host__ __device__ __forceinline__ double sin_f64(double x) {
     // absolute error stays far below the phase's own ulp)
     const double m = rint(x * kOneOverPi);
     x = fma(-m, kPic, fma(-m, kPib, fma(-m, kPia, x)));
-    if (fma(-2.0, rint(0.5 * m), m) != 0.0) x = -x;
+    x = flip_sign(x, low_bits(m));
   }
   const double n = rint(x * kOneOverPi);
   double r = fma(-n, kPia, x);
@@ -124,7 +138,7 @@ __host__ __device__ __forceinline__ double sin_f64(double x) {
   p = horner(p, z, -0x1.5555555555555p-3);      // -1/3!
   const double s = fma(r * z, p, r);
   // (-1)^n from n itself (an integer-valued double; no conversion)
-  return fma(-2.0, rint(0.5 * n), n) != 0.0 ? -s : s;
+  return flip_sign(s, low_bits(n));
 }
 
 // Both at once, for |x| < 2^20 only (the Box-Muller angles lie in
@@ -136,8 +150,8 @@ __host__ __device__ __forceinline__ void sincos_f64(double x, double* s, double*
   sincos_poly(r, ps, pc);
   const double vs = (q & 1) ? pc : ps;
   const double vc = (q & 1) ? ps : pc;
-  *s = (q & 2) ? -vs : vs;
-  *c = ((q + 1) & 2) ? -vc : vc;
+  *s = flip_sign(vs, (uint32_t)q >> 1);
+  *c = flip_sign(vc, (uint32_t)(q + 1) >> 1);
 }
 
 // Reciprocal and square root for the Box-Muller radius, where the operands
