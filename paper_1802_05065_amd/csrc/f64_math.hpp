@@ -113,7 +113,7 @@ constexpr double kPib = 0x1.0b4611a600000p-33;
 constexpr double kPic = 0x1.3198a2e037073p-68;
 
 __host__ __device__ __forceinline__ double sin_f64(double x) {
-  if (!(fabs(x) < 0x1p30)) {
+  if (__builtin_expect(!(fabs(x) < 0x1p30), 0)) {
     // far phases: first take out a multiple of pi the same way (the
     // product exact inside each fma, one rounding per step; the result's
     // absolute error stays far below the phase's own ulp)
