@@ -158,13 +158,14 @@ __host__ __device__ __forceinline__ void sincos_f64(double x, double* s, double*
 // are positive normal numbers of moderate size: the hardware estimate
 // (v_rcp_f64 / v_rsq_f64) refined by Newton-Raphson steps, without the
 // scaling and special-case handling of the general division and sqrt.
-// (Host builds start from a float estimate, coarser than the hardware's,
-// so the host check covers the refinement.)
+// The hardware estimates are good to about 2^29 ulp, 2^-23 relative.  Host
+// builds start from a float estimate pushed off by a further 2^-22, worse
+// than the hardware's, so the host check covers the refinement.
 __host__ __device__ __forceinline__ double rcp_estimate(double d) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rcp(d);
 #else
-  return (double)(1.0f / (float)d);
+  return (double)(1.0f / (float)d) * (1.0 + 0x1p-22);
 #endif
 }
 
@@ -172,7 +173,7 @@ __host__ __device__ __forceinline__ double rsq_estimate(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rsq(x);
 #else
-  return (double)(1.0f / std::sqrt((float)x));
+  return (double)(1.0f / std::sqrt((float)x)) * (1.0 - 0x1p-22);
 #endif
 }
 
