@@ -43,11 +43,10 @@ OPS_FP32C = (40 + 6 + 10 + 5 + 26 + 3 + 2) / 4.0
 # (256 CUs x 128 FP32 lanes per clock x 2.4 GHz)
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # FP64 flops per replica-step of the FP64 kernel as compiled (its own sin,
-# Box-Muller log and sin/cos, the library's sqrt): 10.74 adds + 17.48
-# multiplies + 35.46 FMAs (2 flops) per step from its
-# SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 counters
+# Box-Muller log, sqrt and sin/cos): 11.74 adds + 16.49 multiplies + 34.48
+# FMAs (2 flops) per step from its SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 counters
 # (profiles/slice_kernel_fp64_switching_2p18.md); peak 78.6 TFLOP/s.
-FP64_FLOPS_PER_STEP = 10.74 + 17.48 + 2 * 35.46
+FP64_FLOPS_PER_STEP = 11.74 + 16.49 + 2 * 34.48
 PEAK_FP64_FLOPS = 78.6e12
 
 
