@@ -239,7 +239,7 @@ fpt_status Plan::layout(uint64_t slots) {
   return FPT_OK;
 }
 
-SliceArgs Plan::slice_args(char* ws, uint64_t* hist_dev, uint64_t n_lanes_, int buf) const {
+SliceArgs Plan::slice_args(char* ws, uint64_t* hist, uint64_t lanes, int buf) const {
   SliceArgs a;
   std::memset(&a, 0, sizeof(a));
   a.sets = reinterpret_cast<const SetDev*>(ws + off_sets);
@@ -260,8 +260,8 @@ SliceArgs Plan::slice_args(char* ws, uint64_t* hist_dev, uint64_t n_lanes_, int 
     a.st_set = reinterpret_cast<uint32_t*>(ws + off_alt_set);
   }
   a.st_mt = mt ? reinterpret_cast<uint4*>(ws + off_st_mt) : nullptr;
-  a.n_lanes = n_lanes_;
-  a.hist = reinterpret_cast<unsigned long long*>(hist_dev);
+  a.n_lanes = lanes;
+  a.hist = reinterpret_cast<unsigned long long*>(hist);
   a.mom = reinterpret_cast<MomDev*>(ws + off_mom);
   a.blocks = 0;
   a.refill = 0;
@@ -297,7 +297,7 @@ fpt_status Plan::ensure_host_resources(size_t n_events) {
 
 // Reset counters, results and lane state, then bind every slot's first
 // replica.  `sets_dev` already holds the set table.
-fpt_status Plan::reset_run(char* ws, const SliceArgs& a, uint64_t n_lanes_, int R, bool refill,
+fpt_status Plan::reset_run(char* ws, const SliceArgs& a, uint64_t lanes, int R, bool refill,
                            hipStream_t st) {
   FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(a.ctr),
                           sizeof(Counters) / 8, 0ull, st));
@@ -307,7 +307,7 @@ fpt_status Plan::reset_run(char* ws, const SliceArgs& a, uint64_t n_lanes_, int 
   if (multi && has_alt)  // the regroup's per-set counts
     FPT_HIP(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws + off_group), sets.size(),
                             0ull, st));
-  const uint64_t n_slots = n_lanes_ * (uint64_t)R;
+  const uint64_t n_slots = lanes * (uint64_t)R;
   const uint64_t n_assign = std::min<uint64_t>(n_slots, total_flat);
   FPT_HIP(launch_init(precision == FPT_FP64, a, n_slots, n_assign, st));
   if (refill) FPT_HIP(launch_fill_u64(&a.ctr->cursor, 1, n_assign, st));
