@@ -54,8 +54,9 @@ PEAK_FP64_FLOPS = 78.6e12
 # compiles them for gfx950 (its hot loop's disassembly), by issue class; each
 # class is priced at the rate profiles/isa_rates_gfx950.txt measured for it.
 FP32C_BLOCK_MIX = {
-    "mad_u64_u32_s0": 20,  # Philox products
-    "bitop3_b32_s": 20,    # Philox three-input XORs
+    "mad_u64_u32_s0": 18,  # Philox products (2 of rounds 0-1 formed once per busy loop)
+    "bitop3_b32_s": 16,    # Philox three-input XORs (rounds 2-9)
+    "xor_b32": 3,          # what rounds 0-1 leave per block
     "sin_f32": 6, "cos_f32": 2, "log_f32": 2,
     "sqrt_f32_neg": 2,     # Box-Muller radius, negated operand (VOP3 form)
     "fmac_f32_s": 16,      # phase advance, noise, force, damping

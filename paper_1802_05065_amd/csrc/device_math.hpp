@@ -72,6 +72,86 @@ __device__ __forceinline__ Words philox4x32_10_uniform_key(uint32_t c0, uint32_t
   return Words{c0, c1, c2, c3};
 }
 
+// The generator for a counter whose words 1-3 stay fixed while word 0 (the
+// block index's low half) steps: a replica's blocks between two crossings
+// of a multiple of 2^32.  Of rounds 0 and 1, every part that does not
+// depend on word 0 is formed once (round 0's product of word 2 and the
+// new word 0 it gives, round 1's product of that word, and the words and
+// key XORs they meet); what is left of the two rounds is 2 products and 3
+// two-input XORs instead of 4 products and 4 three-input XORs.  The words
+// equal philox4x32_10's bit for bit (host-checked against the oracle's).
+// M0 = 0xD2511F53 and M1 = 0xCD9E8D57 are the round multipliers, W0 =
+// 0x9E3779B9 and W1 = 0xBB67AE85 the key increments.
+struct PhiloxFixed {
+  uint32_t b;  // c3 ^ k1: round 0's second XOR without hi(M0 c0)
+  uint32_t d;  // lo(M1 c2) ^ (k0 + W0): round 1's first XOR without its product
+  uint32_t e;  // hi(M0 A) ^ (k1 + W1): round 1's second XOR without lo(M0 c0)
+  uint32_t f;  // lo(M0 A): round 1's new word 3
+};
+
+__host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+  return a ^ b ^ c;
+#endif
+}
+
+// (A = hi(M1 c2) ^ c1 ^ k0 is round 0's new word 0.)
+__host__ __device__ __forceinline__ PhiloxFixed philox_fixed_part(uint32_t c1, uint32_t c2,
+                                                                  uint32_t c3, uint32_t k0,
+                                                                  uint32_t k1) {
+  const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+  const uint32_t A = xor3((uint32_t)(pb >> 32), c1, k0);
+  const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)A;
+  PhiloxFixed f;
+  f.b = c3 ^ k1;
+  f.d = (uint32_t)pb ^ (k0 + 0x9E3779B9u);
+  f.e = (uint32_t)(pa >> 32) ^ (k1 + 0xBB67AE85u);
+  f.f = (uint32_t)pa;
+  return f;
+}
+
+// philox4x32_10(c0, c1, c2, c3, k0, k1) given philox_fixed_part(c1, c2, c3,
+// k0, k1); the key is wavefront-uniform as in philox4x32_10_uniform_key.
+__host__ __device__ __forceinline__ Words philox4x32_10_fixed(uint32_t c0,
+                                                              const PhiloxFixed& f,
+                                                              uint32_t k0, uint32_t k1) {
+  // round 0: only the product of word 0 varies
+  const uint64_t pa0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+  const uint32_t n2 = (uint32_t)(pa0 >> 32) ^ f.b;
+  // round 1: only the product of the new word 2 varies
+  const uint64_t pb1 = (uint64_t)0xCD9E8D57u * (uint64_t)n2;
+  c0 = (uint32_t)(pb1 >> 32) ^ f.d;
+  uint32_t c1 = (uint32_t)pb1;
+  uint32_t c2 = (uint32_t)pa0 ^ f.e;
+  uint32_t c3 = f.f;
+  // (formed in the loop on the scalar unit, not held across it: two more
+  // live scalar registers cost the FP32C kernel its eighth resident wave)
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+s"(k0), "+s"(k1));
+#endif
+  k0 += 2u * 0x9E3779B9u;
+  k1 += 2u * 0xBB67AE85u;
+#pragma unroll
+  for (int round = 2; round < 10; ++round) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+s"(k0), "+s"(k1));
+#endif
+    const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+    const uint32_t m2 = xor3((uint32_t)(pa >> 32), c3, k1);
+    c1 = (uint32_t)pb;
+    c3 = (uint32_t)pa;
+    c0 = n0;
+    c2 = m2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Words{c0, c1, c2, c3};
+}
+
 // Words of block j of replica idx: counter (j lo, j hi, idx lo, idx hi),
 // key (seed lo, seed hi).
 __device__ __forceinline__ Words replica_words(uint64_t seed, uint64_t idx,

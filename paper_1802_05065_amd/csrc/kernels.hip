@@ -390,15 +390,18 @@ __device__ __forceinline__ uint32_t blocks_to_cap(const Slot<FP64>& sl, uint64_t
 // MT19937 (active lanes only: a free slot's state is re-seeded when it takes
 // a replica).
 template <bool MT, bool FP64>
+// (`pf`: the generator's parts for the slot's fixed counter words 1-3, for
+// blocks whose low block word does not wrap; null: the full generator.)
 __device__ __forceinline__ Words block_words(const SliceArgs& a, uint64_t n_slots,
                                              uint64_t slot, bool active, MtCarry& mc,
                                              const Slot<FP64>& sl, uint32_t k0,
-                                             uint32_t k1) {
+                                             uint32_t k1, const PhiloxFixed* pf = nullptr) {
   if constexpr (MT) {
     Words w{0u, 0u, 0u, 0u};
     if (active) w = mt_block(a.st_mt, n_slots, slot, mc);
     return w;
   } else {
+    if (pf) return philox4x32_10_fixed((uint32_t)sl.j, *pf, k0, k1);
     return philox4x32_10_uniform_key((uint32_t)sl.j, (uint32_t)(sl.j >> 32),
                                      (uint32_t)sl.idx, (uint32_t)(sl.idx >> 32), k0, k1);
   }
@@ -463,7 +466,7 @@ __device__ __forceinline__ void block_f32(const SliceArgs& a, uint64_t n_slots,
                                           uint64_t lane_g, uint64_t lane_bit, int r0,
                                           const uint64_t* amask, MtCarry* mc,
                                           Slot<false>* s, const SetPar<false>& P, double gA,
-                                          float (*ph_q)[5]) {
+                                          float (*ph_q)[5], const PhiloxFixed* pf = nullptr) {
   const ParF32& p = P.p;
   // generator and normals of every slot first, then the 4 steps with the
   // slots interleaved (independent chains for the scheduler)
@@ -477,7 +480,8 @@ __device__ __forceinline__ void block_f32(const SliceArgs& a, uint64_t n_slots,
     // dependency chain
     gk[r] = block_g4(p, sl.kd, gA);
     const Words w = block_words<MT>(a, n_slots, (uint64_t)(r0 + r) * a.n_lanes + lane_g,
-                                    (amask[r] & lane_bit) != 0, mc[r], sl, P.k0, P.k1);
+                                    (amask[r] & lane_bit) != 0, mc[r], sl, P.k0, P.k1,
+                                    pf ? pf + r : nullptr);
     bm[r] = box_muller_f32(w);
     // all four bias terms exist before the first step, so every step can
     // accumulate into its own (the first otherwise still feeds the rest)
@@ -733,12 +737,20 @@ __device__ __forceinline__ void slice_body(const SliceArgs& a) {
       // Every lane busy: run blocks without the refill test until one of
       // them finishes (its slot refills above in the next block) or the
       // launch ends.  (FP32C only: in the FP64 kernel the second copy of
-      // the block costs more spilled scalar registers than the test.)
-      if (amask[0] == ~0ull) {
+      // the block costs more spilled scalar registers than the test.)  The
+      // loop keeps each lane's replica, so the generator's counter words
+      // 1-3 stay fixed unless a low block word wraps before the launch
+      // ends (a replica past 2^32 blocks): where none can, their part of
+      // the generator is formed once for the loop.
+      const uint32_t left = (uint32_t)(a.blocks - blk);
+      if (amask[0] == ~0ull && __ballot((uint32_t)s[0].j > 0xFFFFFFFFu - (left - 1u)) == 0) {
+        const PhiloxFixed pf = philox_fixed_part((uint32_t)(s[0].j >> 32), (uint32_t)s[0].idx,
+                                                 (uint32_t)(s[0].idx >> 32), P.k0, P.k1);
         for (;;) {
           uint64_t e1[1][4];
           float ph_q[1][5];
-          block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, P, gA, ph_q);
+          block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, P, gA, ph_q,
+                                  &pf);
           threshold_f32(ph_q[0], s[0].e, P.p.th_near_rev, P.p.th_rev, amask[0], e1[0]);
           finish_slot<false>(tab, a, s[0], amask[0], safe[0], e1[0], lane_bit, 0u);
           if (amask[0] != ~0ull || blk + 1 >= a.blocks) break;
