@@ -71,6 +71,9 @@ FP32C_BLOCK_MIX = {
     "fma_f64": 1, "add_f64": 1,   # bias G_k and step count in FP64
     "add_u32": 2,          # block index
 }
+# The multi-set kernel's one-set loop forms the whole generator every block.
+FP32C_MULTI_BLOCK_MIX = {k: v for k, v in FP32C_BLOCK_MIX.items() if k != "xor_b32"}
+FP32C_MULTI_BLOCK_MIX.update({"mad_u64_u32_s0": 20, "bitop3_b32_s": 20})
 
 
 def mix_attainable(mix=FP32C_BLOCK_MIX):
@@ -416,7 +419,7 @@ def batched_roofline(st):
     if kernel_s <= 0:
         return None
     rate = st["replica_steps"] / kernel_s
-    mix = mix_attainable()
+    mix = mix_attainable(FP32C_MULTI_BLOCK_MIX)
     return {"bound": "alu", "achieved": rate * OPS_FP32C / 1e12, "peak": PEAK_LANE_OPS / 1e12,
             "unit": "TOP/s", "frac": rate * OPS_FP32C / PEAK_LANE_OPS,
             "ops_per_replica_step": OPS_FP32C,
