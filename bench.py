@@ -54,7 +54,7 @@ PEAK_FP64_FLOPS = 78.6e12
 # compiles them for gfx950 (its hot loop's disassembly), by issue class; each
 # class is priced at the rate profiles/isa_rates_gfx950.txt measured for it.
 FP32C_BLOCK_MIX = {
-    "mad_u64_u32_s0": 18,  # Philox products (2 of rounds 0-1 formed once per busy loop)
+    "mad_u64_u32_s0": 18,  # Philox products (2 of rounds 0-1 formed once per one-set loop)
     "bitop3_b32_s": 16,    # Philox three-input XORs (rounds 2-9)
     "xor_b32": 3,          # what rounds 0-1 leave per block
     "sin_f32": 6, "cos_f32": 2, "log_f32": 2,
@@ -71,9 +71,6 @@ FP32C_BLOCK_MIX = {
     "fma_f64": 1, "add_f64": 1,   # bias G_k and step count in FP64
     "add_u32": 2,          # block index
 }
-# The multi-set kernel's one-set loop forms the whole generator every block.
-FP32C_MULTI_BLOCK_MIX = {k: v for k, v in FP32C_BLOCK_MIX.items() if k != "xor_b32"}
-FP32C_MULTI_BLOCK_MIX.update({"mad_u64_u32_s0": 20, "bitop3_b32_s": 20})
 
 
 def mix_attainable(mix=FP32C_BLOCK_MIX):
@@ -419,7 +416,7 @@ def batched_roofline(st):
     if kernel_s <= 0:
         return None
     rate = st["replica_steps"] / kernel_s
-    mix = mix_attainable(FP32C_MULTI_BLOCK_MIX)
+    mix = mix_attainable()
     return {"bound": "alu", "achieved": rate * OPS_FP32C / 1e12, "peak": PEAK_LANE_OPS / 1e12,
             "unit": "TOP/s", "frac": rate * OPS_FP32C / PEAK_LANE_OPS,
             "ops_per_replica_step": OPS_FP32C,

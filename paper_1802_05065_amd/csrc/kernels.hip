@@ -768,13 +768,24 @@ __device__ __forceinline__ void slice_body(const SliceArgs& a) {
       if (a.whole_waves) {
         const uint32_t s_first = (uint32_t)__builtin_amdgcn_readlane(
             (int)s[0].set, __ffsll((unsigned long long)amask[0]) - 1);
-        if ((__ballot(s[0].set != s_first) & amask[0]) == 0) {
+        // (FP32C with Philox: also no active lane's low block word may wrap
+        // before the launch ends, so that the generator's fixed counter
+        // words hold for the loop, as in the single-set busy loop)
+        constexpr bool kFixed = !FP64 && !MT;
+        const uint32_t left = (uint32_t)(a.blocks - blk);
+        if ((__ballot(s[0].set != s_first) & amask[0]) == 0 &&
+            (!kFixed ||
+             (__ballot((uint32_t)s[0].j > 0xFFFFFFFFu - (left - 1u)) & amask[0]) == 0)) {
           const SetPar<FP64> Q = load_setpar<FP64>(a.sets, s_first);
           double gQ = 0.0;
+          PhiloxFixed pf{};
           if constexpr (!FP64) {
             gQ = Q.p.gA;
             asm volatile("" : "+v"(gQ));
           }
+          if constexpr (kFixed)
+            pf = philox_fixed_part((uint32_t)(s[0].j >> 32), (uint32_t)s[0].idx,
+                                   (uint32_t)(s[0].idx >> 32), Q.k0, Q.k1);
           for (;;) {
             uint64_t e1[1][4];
             if constexpr (FP64) {
@@ -783,7 +794,7 @@ __device__ __forceinline__ void slice_body(const SliceArgs& a) {
             } else {
               float ph_q[1][5];
               block_f32<MODEL, 1, MT>(a, n_slots, lane_g, lane_bit, 0, amask, mc, s, Q, gQ,
-                                      ph_q);
+                                      ph_q, kFixed ? &pf : nullptr);
               threshold_f32(ph_q[0], s[0].e, Q.p.th_near_rev, Q.p.th_rev, amask[0], e1[0]);
             }
             finish_slot<false>(tab, a, s[0], amask[0], safe[0], e1[0], lane_bit, kInactive);
